@@ -1,0 +1,314 @@
+"""Oracle: WENO point values, numerical flux, residual, SSP-RK3, time step.
+
+Test infrastructure only (see the package docstring).
+
+Paper:
+* Sec. 3.4: split of the optimised linear weights (theta = 3),
+  gamma~+ = (gamma + theta|gamma|)/2, gamma~- = gamma~+ - gamma,
+  sigma^pm = sum gamma~pm, gamma^pm = gamma~pm / sigma^pm; the new smoothness
+  indicator beta~ = beta (1 + gamma^pm beta + (gamma^pm beta)^2) with
+  beta_j = |Omega| int |grad P_j|^2 for the linear candidates; nonlinear
+  weights alpha = gamma^pm / (beta~ + eps)^2, delta = alpha / sum alpha; the
+  split reconstruction R = sigma^+ R^+ - sigma^- R^-.
+* Sec. 2: eq. (semidiscrete) residual, eq. (quadrature) two-point Gauss rule
+  with weights 1/2, eq. (transform) rotation to the face frame, HLLC flux.
+* Sec. 4: the three-stage TVD Runge-Kutta scheme.
+
+Readings:
+* the final reconstruction keeps the factors sigma^pm of the split form and
+  is evaluated about W_i0: R = W_i0 + sigma^+ sum delta^+ (P_j - W_i0)
+  - sigma^- sum delta^- (P_j - W_i0) (equal to the split form because
+  sum delta^pm = 1 and sigma^+ - sigma^- = sum gamma = 1);
+* eps = 1e-3 (the paper leaves it unspecified; with 1e-6 the smooth
+  advection test does not reach third order on meshes of the paper's sizes);
+* HLLC: Toro's contact-restoring solver with the Davis wave-speed estimates
+  S_L = min(u_L - a_L, u_R - a_R), S_R = max(u_L + a_L, u_R + a_R);
+* every face flux is evaluated in a canonical orientation: the left state is
+  the cell with the lower original id, the normal is that cell's outer
+  normal, and both cells use the same value with opposite signs;
+* a transmissive boundary face takes the interior reconstructed state on
+  both sides;
+* time step: dt = CFL min_i 2|Omega_i| / sum_p |l_p| (|u_i . n_p| + c_i), from
+  cell averages (c = 0 and u = a for scalar advection), clamped to t_end - t.
+  The paper instead fixes dt = 0.3 h for its accuracy runs.
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from .weights import Tables, group_row  # noqa: F401
+
+
+@dataclasses.dataclass
+class Physics:
+    equation: str = "euler"     # "euler" or "advection"
+    ax: float = 1.0
+    ay: float = 1.0
+    gamma: float = 1.4
+
+    @property
+    def nvar(self) -> int:
+        return 4 if self.equation == "euler" else 1
+
+
+# --------------------------------------------------------------------------
+# reconstruction (WENO or linear) at the Gauss points of a group of cells
+# --------------------------------------------------------------------------
+
+def _weno_group(g, W, scheme, rows):
+    st = g.st
+    cells = st.cells[rows]
+    rc = st.runtime_cell[rows]                          # [m,S]
+    W0 = W[:, cells]                                    # [V,m]
+    dW = W[:, rc] - W0[:, :, None]                      # [V,m,S]
+    Y = g.Y[rows]                                       # [m,M,2,2]
+    off = g.gp_off[rows]                                # [m,G,2]
+    M = st.spec.M
+    m = cells.size
+    if scheme.mode == "linear":
+        eta = g.eta[rows]                               # [m,G,S]
+        return W0[:, :, None] + np.einsum("mgs,vms->vmg", eta[:, :, 1:], dW[:, :, 1:])
+    dWa = dW[:, :, g.cand_a]                            # [V,m,M]
+    dWb = np.take_along_axis(dW, np.broadcast_to(g.cand_b[rows][None], (W.shape[0], m, M)), axis=2)
+    gx = Y[None, :, :, 0, 0] * dWa + Y[None, :, :, 0, 1] * dWb
+    gy = Y[None, :, :, 1, 0] * dWa + Y[None, :, :, 1, 1] * dWb
+    beta = gx * gx + gy * gy                             # [V,m,M]
+    gam = g.gamma[rows]                                 # [m,G,M]
+    tp = 0.5 * (gam + scheme.theta * np.abs(gam))
+    tm = tp - gam
+    sp = tp.sum(axis=-1, keepdims=True)
+    sm = tm.sum(axis=-1, keepdims=True)
+    gp = tp / sp
+    gm = tm / sm
+    # P_j(x_G) - W_i0 at every point: [V,m,G,M]
+    d = off[None, :, :, None, 0] * gx[:, :, None, :] + off[None, :, :, None, 1] * gy[:, :, None, :]
+    b = beta[:, :, None, :]
+    out = W0[:, :, None].copy()
+    for gw, sig, sgn in ((gp, sp, 1.0), (gm, sm, -1.0)):
+        t = gw[None] * b
+        bt = b * (1.0 + t + t * t)
+        alpha = gw[None] / (bt + scheme.eps) ** 2
+        delta = alpha / alpha.sum(axis=-1, keepdims=True)
+        out = out + sgn * sig[None, :, :, 0] * (delta * d).sum(axis=-1)
+    return out                                          # [V,m,G]
+
+
+def reconstruct_face_states(tables: Tables, W, cells=None):
+    """Reconstructed values at the 2n Gauss points of each requested cell.
+
+    Returns a dict cell -> array [V, 2n] (point g = 2k + q is the q-th Gauss
+    point of face k, ordered from v_k to v_{k+1})."""
+    W = np.asarray(W, dtype=np.float64)
+    if cells is None:
+        cells = np.flatnonzero(tables.loc >= 0)
+    cells = np.asarray(cells, dtype=np.int64)
+    out = {}
+    for nf_value, g in tables.groups.items():
+        loc = tables.loc[cells]
+        mine = cells[(loc >> 32) == nf_value]
+        if mine.size == 0:
+            continue
+        rows = (tables.loc[mine] & 0xFFFFFFFF).astype(np.int64)
+        step = 8192
+        for i in range(0, rows.size, step):
+            R = _weno_group(g, W, tables.scheme, rows[i:i + step])
+            for c, r in zip(mine[i:i + step], np.moveaxis(R, 1, 0)):
+                out[int(c)] = r
+    return out
+
+
+# --------------------------------------------------------------------------
+# fluxes
+# --------------------------------------------------------------------------
+
+def physical_flux(Wv, nx, ny, gamma):
+    """Exact Euler flux F(W).n through a face with unit normal (nx, ny)."""
+    rho, mu, mv, E = Wv
+    u, v = mu / rho, mv / rho
+    p = (gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+    un = u * nx + v * ny
+    return np.stack([rho * un, mu * un + p * nx, mv * un + p * ny, (E + p) * un])
+
+
+def hllc_flux(WL, WR, nx, ny, gamma):
+    """HLLC flux for the Euler equations through a face with unit normal
+    (nx, ny), from the left state WL to the right state WR ([4, ...] arrays).
+    The states are rotated into the face frame (eq. (transform)), the HLLC
+    flux is evaluated there, and rotated back."""
+    def prim(Wv):
+        rho, mu, mv, E = Wv
+        un = (mu * nx + mv * ny) / rho
+        ut = (-mu * ny + mv * nx) / rho
+        p = (gamma - 1.0) * (E - 0.5 * rho * (un * un + ut * ut))
+        a = np.sqrt(gamma * p / rho)
+        return rho, un, ut, p, E, a
+
+    rL, uL, vL, pL, EL, aL = prim(WL)
+    rR, uR, vR, pR, ER, aR = prim(WR)
+    SL = np.minimum(uL - aL, uR - aR)
+    SR = np.maximum(uL + aL, uR + aR)
+    Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) / (rL * (SL - uL) - rR * (SR - uR))
+
+    def flux(r, u, v, p, E):
+        return np.stack([r * u, r * u * u + p, r * u * v, (E + p) * u])
+
+    def star(r, u, v, p, E, S):
+        c = r * (S - u) / (S - Ss)
+        return np.stack([c, c * Ss, c * v, c * (E / r + (Ss - u) * (Ss + p / (r * (S - u))))])
+
+    FL = flux(rL, uL, vL, pL, EL)
+    FR = flux(rR, uR, vR, pR, ER)
+    UL = np.stack([rL, rL * uL, rL * vL, EL])
+    UR = np.stack([rR, rR * uR, rR * vR, ER])
+    FsL = FL + SL * (star(rL, uL, vL, pL, EL, SL) - UL)
+    FsR = FR + SR * (star(rR, uR, vR, pR, ER, SR) - UR)
+    F = np.where(0.0 <= SL, FL, np.where(0.0 <= Ss, FsL, np.where(0.0 < SR, FsR, FR)))
+    Fn, Ft = F[1], F[2]
+    return np.stack([F[0], Fn * nx - Ft * ny, Fn * ny + Ft * nx, F[3]])
+
+
+def upwind_flux(uL, uR, nx, ny, ax, ay):
+    an = ax * nx + ay * ny
+    return np.where(an >= 0.0, an * uL, an * uR)
+
+
+def _face_flux(physics, WL, WR, nx, ny):
+    if physics.equation == "euler":
+        return hllc_flux(WL, WR, nx, ny, physics.gamma)
+    return upwind_flux(WL, WR, nx, ny, physics.ax, physics.ay)
+
+
+# --------------------------------------------------------------------------
+# residual, time step, RK3
+# --------------------------------------------------------------------------
+
+def residual(tables: Tables, W, physics: Physics, cells=None):
+    """L(W) = -(1/|Omega_i|) sum_p |l_p| sum_k (1/2) F(x_pk) . n_p for the
+    requested cells (default: all).  Returns [V, len(cells)]."""
+    W = np.asarray(W, dtype=np.float64)
+    conn = tables.conn
+    if cells is None:
+        cells = np.arange(conn.nf.size)
+    cells = np.asarray(cells, dtype=np.int64)
+    nb = conn.nbr[cells]
+    need = np.unique(np.concatenate([cells, nb[nb >= 0]]))
+    R = reconstruct_face_states(tables, W, need)
+    V = W.shape[0]
+    L = np.zeros((V, cells.size))
+    for idx, i in enumerate(cells):
+        gi, ri = group_row(tables, int(i))
+        acc = np.zeros(V)
+        for k in range(int(conn.nf[i])):
+            c = int(conn.nbr[i, k])
+            Ri = R[int(i)]
+            if c < 0:
+                nx, ny = gi.normal[ri, k]
+                ln = gi.length[ri, k]
+                F0 = _face_flux(physics, Ri[:, 2 * k], Ri[:, 2 * k], nx, ny)
+                F1 = _face_flux(physics, Ri[:, 2 * k + 1], Ri[:, 2 * k + 1], nx, ny)
+                acc += ln * 0.5 * (F0 + F1)
+                continue
+            kp = int(conn.nbr_face[i, k])
+            Rc = R[c]
+            if i < c:      # this cell is the left state
+                nx, ny = gi.normal[ri, k]
+                ln = gi.length[ri, k]
+                F0 = _face_flux(physics, Ri[:, 2 * k], Rc[:, 2 * kp + 1], nx, ny)
+                F1 = _face_flux(physics, Ri[:, 2 * k + 1], Rc[:, 2 * kp], nx, ny)
+                acc += ln * 0.5 * (F0 + F1)
+            else:
+                gc, rcr = group_row(tables, c)
+                nx, ny = gc.normal[rcr, kp]
+                ln = gc.length[rcr, kp]
+                F0 = _face_flux(physics, Rc[:, 2 * kp + 1], Ri[:, 2 * k], nx, ny)
+                F1 = _face_flux(physics, Rc[:, 2 * kp], Ri[:, 2 * k + 1], nx, ny)
+                acc -= ln * 0.5 * (F0 + F1)
+        L[:, idx] = -acc / gi.area[ri]
+    return L
+
+
+def residual_vectorized(tables: Tables, W, physics: Physics):
+    """Same as ``residual`` for all cells, vectorised over cells per face slot
+    (used for large meshes; identical arithmetic per face)."""
+    W = np.asarray(W, dtype=np.float64)
+    conn = tables.conn
+    N = conn.nf.size
+    V = W.shape[0]
+    R = np.zeros((V, N, 8))
+    normal = np.zeros((N, 4, 2))
+    length = np.zeros((N, 4))
+    area = np.zeros(N)
+    for nf_value, g in tables.groups.items():
+        cells = g.st.cells
+        step = 8192
+        for i in range(0, cells.size, step):
+            rows = np.arange(i, min(cells.size, i + step))
+            R[:, cells[rows], :2 * nf_value] = _weno_group(g, W, tables.scheme, rows)
+        normal[cells] = g.normal
+        length[cells] = g.length
+        area[cells] = g.area
+    acc = np.zeros((V, N))
+    ids = np.arange(N)
+    for k in range(4):
+        valid = k < conn.nf
+        c = conn.nbr[:, k]
+        kp = conn.nbr_face[:, k]
+        bnd = valid & (c < 0)
+        inn = valid & (c >= 0)
+        cc = np.where(inn, c, ids)
+        kk = np.where(inn, kp, 0)
+        left = ids < cc
+        # unused face slots (k >= n) take a valid state; their flux is discarded
+        Ri0 = np.where(valid[None], R[:, ids, 2 * k], R[:, ids, 0])
+        Ri1 = np.where(valid[None], R[:, ids, 2 * k + 1], R[:, ids, 0])
+        Rc0 = np.where(inn[None], R[:, cc, 2 * kk + 1], Ri0)   # neighbour value at my point 0
+        Rc1 = np.where(inn[None], R[:, cc, 2 * kk], Ri1)
+        nL = np.where((left | bnd)[:, None], normal[:, k], normal[cc, kk])
+        nL = np.where(valid[:, None], nL, 1.0 / np.sqrt(2.0))
+        lL = np.where(left | bnd, length[:, k], length[cc, kk])
+        WL0 = np.where((left | bnd)[None], Ri0, Rc0)
+        WR0 = np.where((left | bnd)[None], Rc0, Ri0)
+        WL1 = np.where((left | bnd)[None], Ri1, Rc1)
+        WR1 = np.where((left | bnd)[None], Rc1, Ri1)
+        F0 = _face_flux(physics, WL0 if V > 1 else WL0[0], WR0 if V > 1 else WR0[0], nL[:, 0], nL[:, 1])
+        F1 = _face_flux(physics, WL1 if V > 1 else WL1[0], WR1 if V > 1 else WR1[0], nL[:, 0], nL[:, 1])
+        F0 = np.reshape(F0, (V, N))
+        F1 = np.reshape(F1, (V, N))
+        s = np.where(left | bnd, 1.0, -1.0)
+        contrib = lL * 0.5 * (F0 + F1) * s
+        acc += np.where(valid[None], contrib, 0.0)
+    return -acc / area[None, :]
+
+
+def cfl_dt(tables: Tables, W, physics: Physics, cfl: float):
+    """CFL-limited time step from cell averages."""
+    W = np.asarray(W, dtype=np.float64)
+    best = np.inf
+    for g in tables.groups.values():
+        cells = g.st.cells
+        if physics.equation == "euler":
+            rho, mu, mv, E = W[:, cells]
+            u, v = mu / rho, mv / rho
+            p = (physics.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v))
+            c = np.sqrt(physics.gamma * p / rho)
+        else:
+            u = np.full(cells.size, physics.ax)
+            v = np.full(cells.size, physics.ay)
+            c = np.zeros(cells.size)
+        s = np.zeros(cells.size)
+        for k in range(g.st.spec.n):
+            un = u * g.normal[:, k, 0] + v * g.normal[:, k, 1]
+            s += g.length[:, k] * (np.abs(un) + c)
+        best = min(best, float((2.0 * g.area / s).min()))
+    return cfl * best
+
+
+def rk3_step(tables: Tables, W, physics: Physics, dt: float, resid=None):
+    """One step of the three-stage TVD Runge-Kutta scheme of Sec. 4."""
+    resid = resid or (lambda X: residual_vectorized(tables, X, physics))
+    Wn = np.asarray(W, dtype=np.float64)
+    W1 = Wn + dt * resid(Wn)
+    W2 = 0.75 * Wn + 0.25 * (W1 + dt * resid(W1))
+    return Wn / 3.0 + 2.0 / 3.0 * (W2 + dt * resid(W2))

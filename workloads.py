@@ -1,0 +1,379 @@
+"""Seeded synthetic inputs: meshes, initial cell averages and exact solutions.
+
+This module is shared by the oracle, the tests and the benchmark as the single
+source of *inputs*.  It contains none of the scheme's arithmetic (no stencils,
+no least squares, no weights, no fluxes): only node coordinates, cell-node
+lists, and cell averages of closed-form fields, computed by a plain
+high-order quadrature.
+
+Meshes
+------
+All meshes are structured-derived: an ``nx`` by ``ny`` grid of squares of
+side ``h`` whose interior nodes are moved by a seeded uniform jitter, each
+square kept as one counter-clockwise quadrilateral or split into two
+counter-clockwise triangles along its (i,j)-(i+1,j+1) diagonal.  The paper's
+own test meshes (the "regular" and "irregular" families of its accuracy
+section) exist only as figures; these jittered grids stand in for them.
+
+* RNG: ``numpy.random.Generator(PCG64(seed))``; the jitter draws dx then dy,
+  uniform in [-a h, a h], per interior node in row-major (j, i) order.
+* Nodes on the domain boundary never move.  For periodic domains the seam
+  nodes are duplicated, the duplicates offset by exactly the period, and
+  ``node_id`` gives every node its canonical (wrapped) id.
+* Inversion guard (a >= 0.25): up to five rounds; in each round every cell
+  whose signed area is below 0.05 times its undeformed area halves the
+  displacement of each of its nodes (the fifth time: sets it to zero).
+  After the last round no cell is below the threshold.
+
+The state layout everywhere is ``W[v, cell]`` (variables major), float64, in
+the mesh's original cell order.
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+
+import numpy as np
+
+GAMMA = 1.4
+
+
+@dataclasses.dataclass
+class Mesh:
+    node_xy: np.ndarray          # float64 [n_nodes, 2]
+    cell_nodes: np.ndarray       # int32 [n_cells, 4]; triangles have -1 in slot 3
+    node_id: np.ndarray | None   # int32 [n_nodes] canonical ids (periodic), or None
+    period: tuple                # (px, py); 0 = not periodic in that axis
+    bc: str                      # "periodic" or "transmissive"
+    h: float                     # nominal cell size
+    name: str = ""
+
+    @property
+    def n_cells(self) -> int:
+        return int(self.cell_nodes.shape[0])
+
+    @property
+    def n_nodes(self) -> int:
+        return int(self.node_xy.shape[0])
+
+    def n_faces_of(self) -> np.ndarray:
+        return np.where(self.cell_nodes[:, 3] < 0, 3, 4).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# mesh construction
+# --------------------------------------------------------------------------
+
+def _cells_from_split(nx: int, ny: int, split: np.ndarray) -> np.ndarray:
+    """Cell-node list in row-major square order; a split square gives the
+    triangles (i,j),(i+1,j),(i+1,j+1) then (i,j),(i+1,j+1),(i,j+1)."""
+    jj, ii = np.meshgrid(np.arange(ny), np.arange(nx), indexing="ij")
+    n00 = (jj * (nx + 1) + ii).ravel()
+    n10 = n00 + 1
+    n11 = n00 + nx + 2
+    n01 = n00 + nx + 1
+    sp = split.ravel()
+    cnt = np.where(sp, 2, 1)
+    start = np.cumsum(cnt) - cnt
+    total = int(cnt.sum())
+    cells = np.full((total, 4), -1, dtype=np.int32)
+    q = ~sp
+    cells[start[q]] = np.stack([n00[q], n10[q], n11[q], n01[q]], axis=1)
+    s0 = start[sp]
+    cells[s0, 0] = n00[sp]
+    cells[s0, 1] = n10[sp]
+    cells[s0, 2] = n11[sp]
+    cells[s0 + 1, 0] = n00[sp]
+    cells[s0 + 1, 1] = n11[sp]
+    cells[s0 + 1, 2] = n01[sp]
+    return cells
+
+
+def signed_areas(node_xy: np.ndarray, cell_nodes: np.ndarray) -> np.ndarray:
+    """Shoelace signed area of every cell (input validation / guard only)."""
+    nf = np.where(cell_nodes[:, 3] < 0, 3, 4)
+    x = node_xy[np.maximum(cell_nodes, 0), 0]
+    y = node_xy[np.maximum(cell_nodes, 0), 1]
+    a = np.zeros(cell_nodes.shape[0])
+    for k in range(4):
+        kn = np.where(k + 1 < nf, k + 1, 0)
+        valid = k < nf
+        xk = x[:, k]
+        yk = y[:, k]
+        xn = np.take_along_axis(x, kn[:, None], 1)[:, 0]
+        yn = np.take_along_axis(y, kn[:, None], 1)[:, 0]
+        a += np.where(valid, xk * yn - xn * yk, 0.0)
+    return 0.5 * a
+
+
+def grid_mesh(nx: int, ny: int, lx: float, ly: float, split, jitter: float,
+              seed, periodic: bool, name: str = "") -> Mesh:
+    """Jittered structured-derived mesh on [0,lx] x [0,ly].
+
+    ``split`` is "quad", "tri" or a boolean array [ny, nx] (True = split the
+    square into two triangles).  ``seed`` is an int or a SeedSequence.
+    """
+    h = lx / nx
+    if isinstance(split, str):
+        split = np.full((ny, nx), split == "tri")
+    split = np.asarray(split, dtype=bool)
+    xs = np.linspace(0.0, lx, nx + 1)
+    ys = np.linspace(0.0, ly, ny + 1)
+    xs[-1] = lx
+    ys[-1] = ly
+    X, Y = np.meshgrid(xs, ys, indexing="xy")
+    node_xy = np.stack([X.ravel(), Y.ravel()], axis=1).astype(np.float64)
+    cells = _cells_from_split(nx, ny, split)
+
+    rng = np.random.Generator(np.random.PCG64(seed))
+    interior = np.zeros((ny + 1, nx + 1), dtype=bool)
+    interior[1:-1, 1:-1] = True
+    idx = np.flatnonzero(interior.ravel())
+    disp = np.zeros_like(node_xy)
+    if jitter > 0 and idx.size:
+        disp[idx] = rng.uniform(-jitter * h, jitter * h, size=(idx.size, 2))
+    base_area = np.where(cells[:, 3] < 0, 0.5 * h * h, h * h)
+    xy = node_xy + disp
+    if jitter >= 0.25:
+        halvings = np.zeros(node_xy.shape[0], dtype=np.int32)
+        for _ in range(5):
+            a = signed_areas(xy, cells)
+            bad = a < 0.05 * base_area
+            if not bad.any():
+                break
+            nodes = np.unique(cells[bad][cells[bad] >= 0])
+            halvings[nodes] += 1
+            disp[nodes] *= 0.5
+            disp[nodes[halvings[nodes] >= 5]] = 0.0
+            xy = node_xy + disp
+    node_xy = xy
+    a = signed_areas(node_xy, cells)
+    if not (a > 0).all():
+        raise RuntimeError("mesh generator produced a non-positive cell area")
+    node_id = None
+    period = (0.0, 0.0)
+    if periodic:
+        jj, ii = np.meshgrid(np.arange(ny + 1), np.arange(nx + 1), indexing="ij")
+        node_id = ((jj % ny) * nx + (ii % nx)).ravel().astype(np.int32)
+        period = (float(lx), float(ly))
+    return Mesh(node_xy=node_xy, cell_nodes=cells, node_id=node_id, period=period,
+                bc="periodic" if periodic else "transmissive", h=h, name=name)
+
+
+# --------------------------------------------------------------------------
+# the five workloads (plus refinements used for convergence studies)
+# --------------------------------------------------------------------------
+
+def mesh_c1(n: int = 20, jitter: float = 0.10, seed=1) -> Mesh:
+    """Scalar advection mesh: n x n squares on [0,2]^2, all split, periodic."""
+    return grid_mesh(n, n, 2.0, 2.0, "tri", jitter, seed, True, name=f"tri{n}")
+
+
+def mesh_c2q(n: int = 400, jitter: float = 0.20, seed=2) -> Mesh:
+    return grid_mesh(n, n, 2.0, 2.0, "quad", jitter, seed, True, name=f"quad{n}")
+
+
+def mesh_c2t(n: int = 283, jitter: float = 0.20, seed=3) -> Mesh:
+    return grid_mesh(n, n, 2.0, 2.0, "tri", jitter, seed, True, name=f"tri{n}")
+
+
+def mesh_c3(n: int = 1340, jitter: float = 0.15, seed=4, band: float = 0.05) -> Mesh:
+    """Rotated shock tube on [0,1]^2: squares whose centre lies within ``band``
+    of the interface line are split; transmissive boundaries."""
+    h = 1.0 / n
+    c = (np.arange(n) + 0.5) * h
+    cx, cy = np.meshgrid(c, c, indexing="xy")
+    nx_, ny_ = math.cos(math.pi / 6), math.sin(math.pi / 6)
+    dist = np.abs((cx - 0.5) * nx_ + (cy - 0.5) * ny_)
+    return grid_mesh(n, n, 1.0, 1.0, dist < band, jitter, seed, False, name=f"sod{n}")
+
+
+def mesh_c5(n: int = 3264, block: int = 64, jitter: float = 0.30, seed=6) -> Mesh:
+    """Large mixed periodic mesh on [0,2]^2: n x n squares in block x block
+    tiles, checkerboard; tiles with (bi + bj) odd are split into triangles."""
+    b = np.arange(n) // block
+    bj, bi = np.meshgrid(b, b, indexing="ij")
+    split = ((bi + bj) % 2) == 1
+    return grid_mesh(n, n, 2.0, 2.0, split, jitter, seed, True, name=f"mixed{n}")
+
+
+def c4_instances(count: int = 256, seed: int = 5, nmin: float = 2e3, nmax: float = 2e5):
+    """Parameters of the batched workload: per instance (kind, n, jitter, seed).
+
+    N_k is log-uniform in [nmin, nmax]; the mesh type is a fair coin; the
+    jitter amplitude is uniform in [0, 0.3]; the mesh seed is the k-th child
+    of SeedSequence(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    logn = rng.uniform(math.log(nmin), math.log(nmax), size=count)
+    is_tri = rng.random(count) < 0.5
+    amp = rng.uniform(0.0, 0.3, size=count)
+    children = np.random.SeedSequence(seed).spawn(count)
+    out = []
+    for k in range(count):
+        nk = math.exp(logn[k])
+        if is_tri[k]:
+            n = max(4, int(round(math.sqrt(nk / 2))))
+        else:
+            n = max(4, int(round(math.sqrt(nk))))
+        out.append(("tri" if is_tri[k] else "quad", n, float(amp[k]), children[k]))
+    return out
+
+
+def mesh_c4(k: int, count: int = 256) -> Mesh:
+    kind, n, amp, ss = c4_instances(count)[k]
+    return grid_mesh(n, n, 2.0, 2.0, kind, amp, ss, True, name=f"batch{k}")
+
+
+# --------------------------------------------------------------------------
+# cell averages by quadrature (input preparation only)
+# --------------------------------------------------------------------------
+
+def _triangle_rule(q: int):
+    """Collapsed (Duffy) Gauss-Legendre rule on the reference triangle
+    {(s,t): s,t >= 0, s + t <= 1}; exact for total degree 2q - 2."""
+    g, w = np.polynomial.legendre.leggauss(q)
+    g = 0.5 * (g + 1.0)
+    w = 0.5 * w
+    U, V = np.meshgrid(g, g, indexing="ij")
+    WU, WV = np.meshgrid(w, w, indexing="ij")
+    s = U.ravel()
+    t = (V * (1.0 - U)).ravel()
+    wt = (WU * WV * (1.0 - U)).ravel()
+    return s, t, wt  # weights sum to 1/2
+
+
+def cell_averages(mesh: Mesh, fn, nvar: int, q: int = 4, chunk: int = 1 << 18) -> np.ndarray:
+    """Average of ``fn(x, y) -> [nvar, ...]`` over every cell, integrating a
+    fan of triangles from vertex 0 with a collapsed Gauss rule."""
+    s, t, wt = _triangle_rule(q)
+    out = np.empty((nvar, mesh.n_cells))
+    cn = mesh.cell_nodes
+    for c0 in range(0, mesh.n_cells, chunk):
+        c1 = min(mesh.n_cells, c0 + chunk)
+        nodes = cn[c0:c1]
+        nf = np.where(nodes[:, 3] < 0, 3, 4)
+        p = mesh.node_xy[np.maximum(nodes, 0)]  # [m, 4, 2]
+        acc = np.zeros((nvar, c1 - c0))
+        area = np.zeros(c1 - c0)
+        for k in (1, 2):
+            valid = np.ones(c1 - c0, dtype=bool) if k == 1 else (nf == 4)
+            a = p[:, 0]
+            b = p[:, k]
+            c = p[:, k + 1]
+            e1 = b - a
+            e2 = c - a
+            jac = e1[:, 0] * e2[:, 1] - e1[:, 1] * e2[:, 0]
+            x = a[:, None, 0] + e1[:, None, 0] * s[None] + e2[:, None, 0] * t[None]
+            y = a[:, None, 1] + e1[:, None, 1] * s[None] + e2[:, None, 1] * t[None]
+            f = np.asarray(fn(x, y))  # [nvar, m, nq]
+            contrib = (f * wt[None, None, :]).sum(axis=-1) * jac[None, :]
+            acc += np.where(valid[None, :], contrib, 0.0)
+            area += np.where(valid, 0.5 * jac, 0.0)
+        out[:, c0:c1] = acc / area[None, :]
+    return out
+
+
+# --------------------------------------------------------------------------
+# closed-form fields
+# --------------------------------------------------------------------------
+
+def density_wave_scalar(t: float = 0.0, a=(1.0, 1.0)):
+    def f(x, y):
+        return (1.0 + 0.2 * np.sin(np.pi * ((x - a[0] * t) + (y - a[1] * t))))[None]
+    return f
+
+
+def primitive_to_conserved(rho, u, v, p, gamma=GAMMA):
+    return np.stack([rho, rho * u, rho * v, p / (gamma - 1.0) + 0.5 * rho * (u * u + v * v)])
+
+
+def density_wave_euler(t: float = 0.0, gamma=GAMMA):
+    """rho = 1 + 0.2 sin(pi(x + y - 2t)), u = v = p = 1 (exact for all t)."""
+    def f(x, y):
+        rho = 1.0 + 0.2 * np.sin(np.pi * (x + y - 2.0 * t))
+        one = np.ones_like(rho)
+        return primitive_to_conserved(rho, one, one, one, gamma)
+    return f
+
+
+def wave_vortex_euler(strength: float = 5.0, centre=(1.0, 1.0), scale: float = 5.0,
+                      gamma=GAMMA):
+    """Density wave times an isentropic vortex evaluated at
+    (xb, yb) = scale * (x - xc, y - yc) (initial data of the large mixed mesh)."""
+    def f(x, y):
+        xb = scale * (x - centre[0])
+        yb = scale * (y - centre[1])
+        r2 = xb * xb + yb * yb
+        du = strength / (2 * np.pi) * np.exp(0.5 * (1 - r2)) * (-yb)
+        dv = strength / (2 * np.pi) * np.exp(0.5 * (1 - r2)) * xb
+        dT = -(gamma - 1) * strength ** 2 / (8 * gamma * np.pi ** 2) * np.exp(1 - r2)
+        rho = (1.0 + 0.2 * np.sin(np.pi * (x + y))) * (1 + dT) ** (1 / (gamma - 1))
+        p = (1 + dT) ** (gamma / (gamma - 1))
+        return primitive_to_conserved(rho, 1.0 + du, 1.0 + dv, p, gamma)
+    return f
+
+
+def rotated_sod(angle_deg: float = 30.0, gamma=GAMMA):
+    """Sod states (1,0,0,1) | (0.125,0,0,0.1) across the line through
+    (0.5,0.5) with unit normal (cos a, sin a); left where (x-0.5,y-0.5).n < 0."""
+    ca, sa = math.cos(math.radians(angle_deg)), math.sin(math.radians(angle_deg))
+
+    def f(x, y):
+        left = ((x - 0.5) * ca + (y - 0.5) * sa) < 0
+        rho = np.where(left, 1.0, 0.125)
+        p = np.where(left, 1.0, 0.1)
+        z = np.zeros_like(rho)
+        return primitive_to_conserved(rho, z, z, p, gamma)
+    return f
+
+
+def sod_cell_values(mesh: Mesh, angle_deg: float = 30.0, gamma=GAMMA) -> np.ndarray:
+    """Sod initial data sampled at vertex averages (a discontinuous field has
+    no useful quadrature; the cell takes the state at its vertex average)."""
+    cn = mesh.cell_nodes
+    nf = np.where(cn[:, 3] < 0, 3, 4)
+    p = mesh.node_xy[np.maximum(cn, 0)]
+    cx = (p[:, 0, 0] + p[:, 1, 0] + p[:, 2, 0] + np.where(nf == 4, p[:, 3, 0], 0.0)) / nf
+    cy = (p[:, 0, 1] + p[:, 1, 1] + p[:, 2, 1] + np.where(nf == 4, p[:, 3, 1], 0.0)) / nf
+    return rotated_sod(angle_deg, gamma)(cx, cy)
+
+
+def seeded_state(mesh: Mesh, nvar: int, seed: int, amp: float = 0.1) -> np.ndarray:
+    """A smooth field plus seeded cell noise: a generic non-trivial state for
+    parity tests (positive density and pressure for the Euler case)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    if nvar == 1:
+        base = cell_averages(mesh, density_wave_scalar(0.0), 1, q=3)
+    else:
+        base = cell_averages(mesh, density_wave_euler(0.0), 4, q=3)
+    noise = rng.uniform(-amp, amp, size=base.shape)
+    if nvar == 4:
+        noise[1:3] *= 1.0
+        noise[3] *= 2.0
+    return base + noise
+
+
+# --------------------------------------------------------------------------
+# named workloads
+# --------------------------------------------------------------------------
+
+WORKLOADS = {
+    "c1": dict(equation="advection", t_end=0.2, cfl=0.5, nvar=1),
+    "c2q": dict(equation="euler", t_end=0.5, cfl=0.5, nvar=4),
+    "c2t": dict(equation="euler", t_end=0.5, cfl=0.5, nvar=4),
+    "c3": dict(equation="euler", t_end=0.2, cfl=0.5, nvar=4),
+    "c4": dict(equation="euler", steps=100, cfl=0.5, nvar=4),
+    "c5": dict(equation="euler", steps=50, cfl=0.5, nvar=4),
+}
+
+
+def initial_state(name: str, mesh: Mesh, q: int | None = None) -> np.ndarray:
+    if name == "c1":
+        return cell_averages(mesh, density_wave_scalar(0.0), 1, q=q or 5)
+    if name in ("c2q", "c2t", "c4"):
+        return cell_averages(mesh, density_wave_euler(0.0), 4, q=q or 4)
+    if name == "c3":
+        return sod_cell_values(mesh)
+    if name == "c5":
+        return cell_averages(mesh, wave_vortex_euler(), 4, q=q or 2)
+    raise KeyError(name)
