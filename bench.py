@@ -1,0 +1,208 @@
+"""Benchmark: cell-stage updates per second of the WENO-3 residual inside
+SSP-RK3 steps on one MI355X, with the HBM roofline of the dominant kernel and
+the oracle timed on the host as a baseline.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5|c2q|c2t|c3|c1]
+                [--precision fp32|fp64] [--no-cpu-baseline] [--no-check]
+
+A step is one full SSP-RK3 step: the CFL time step, then three stages of
+reconstruction, flux, residual gather and stage combination, all on the
+device.  Inputs are synthetic (seeded meshes and closed-form initial data)
+and resident in HBM before the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# Algorithmic bytes of the reconstruction kernel per cell (minimal table
+# representation, gamma unsplit): stencil indices 4(S-1), Gauss-point offsets
+# 4n, candidate operators 4M and linear weights 2nM values of p bytes, and
+# the cell's own state V * 8 bytes.  Face states written for the flux kernel
+# are implementation traffic and are not counted.
+def recon_bytes(nf, p, nvar):
+    S, M = (13, 12) if nf == 4 else (10, 9)
+    return 4 * (S - 1) + p * (4 * nf + 4 * M + 2 * nf * M) + nvar * 8
+
+
+# Whole cell-stage (both kernels): recon bytes plus the face table (3n
+# values + 4 bytes of pairing) and the state traffic of the stage
+# combination: W_in read, W_out written, W^n read in two of three stages.
+def stage_bytes(nf, p, nvar):
+    return recon_bytes(nf, p, nvar) - nvar * 8 + 4 + p * 3 * nf + (8 / 3) * nvar * 8
+
+
+def make_workload(name):
+    import workloads as wl
+    if name == "c5":
+        return wl.mesh_c5(), "c5", "mixed 3264x3264 squares on [0,2]^2, 64x64 checkerboard, 30% jitter, periodic; density wave x vortex"
+    if name == "c2q":
+        return wl.mesh_c2q(), "c2q", "400x400 quads on [0,2]^2, 20% jitter, periodic; density wave"
+    if name == "c2t":
+        return wl.mesh_c2t(), "c2t", "283x283x2 triangles on [0,2]^2, 20% jitter, periodic; density wave"
+    if name == "c3":
+        return wl.mesh_c3(), "c3", "1340x1340 squares on [0,1]^2 with a triangle band, 15% jitter, transmissive; rotated Sod"
+    if name == "c1":
+        return wl.mesh_c1(), "c1", "20x20x2 triangles on [0,2]^2, 10% jitter, periodic; scalar density wave"
+    raise SystemExit(f"unknown config {name}")
+
+
+def cpu_baseline(seconds_hint=20.0):
+    """The oracle (FP64 NumPy, as it stands) on a bounded sample of the same
+    workload kind: a 128x128-square mixed periodic mesh with the same block
+    checkerboard, jitter and initial data, one residual per stage of
+    SSP-RK3 steps until about ``seconds_hint`` seconds have passed."""
+    import workloads as wl
+    from oracle import weights as ow
+    from oracle import scheme as osc
+    mesh = wl.mesh_c5(n=128, block=64, jitter=0.30, seed=6)
+    T = ow.precompute(mesh)
+    W = wl.initial_state("c5", mesh)
+    ph = osc.Physics("euler")
+    dt = osc.cfl_dt(T, W, ph, 0.5)
+    t0 = time.perf_counter()
+    steps = 0
+    while True:
+        W = osc.rk3_step(T, W, ph, dt)
+        steps += 1
+        el = time.perf_counter() - t0
+        if el > seconds_hint or steps >= 50:
+            break
+    rate = mesh.n_cells * 3 * steps / el
+    return {"value": rate, "unit": "cell-stage updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"oracle rk3 on a {mesh.n_cells}-cell mixed mesh (128x128 squares, "
+                      f"64x64 checkerboard, 30% jitter), {steps} steps, {el:.1f} s, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="c5")
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the FP64 reference run")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-mesh path "
+              "has no multi-GPU decomposition in this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+    import paper_1712_08317_amd as uw
+
+    t0 = time.perf_counter()
+    mesh, cname, desc = make_workload(args.config)
+    log(f"mesh {cname}: {mesh.n_cells} cells ({time.perf_counter() - t0:.1f} s)")
+    t1 = time.perf_counter()
+    M = uw.Mesh.from_workload(mesh, device=0)
+    log(f"upload/connectivity/stencils {time.perf_counter() - t1:.1f} s")
+    t1 = time.perf_counter()
+    diag = M.precompute()
+    log(f"FP64 precompute {time.perf_counter() - t1:.1f} s; max|gamma| raw "
+        f"{diag['max_abs_gamma_raw']:.3g} opt {diag['max_abs_gamma_opt']:.3g}")
+    eq = uw.UW_ADVECTION if cname == "c1" else uw.UW_EULER
+    nvar = 1 if eq == uw.UW_ADVECTION else 4
+    W0 = wl.initial_state(cname, mesh)
+    W0i = M.to_internal(W0)
+    del mesh
+    dev = torch.device("cuda:0")
+    prec = uw.UW_FP32 if args.precision == "fp32" else uw.UW_FP64
+    phys = uw.make_physics(eq, 1.0, 1.0, 1.4, prec)
+    W = torch.from_numpy(W0i).to(dev)
+    t = torch.zeros(1, dtype=torch.float64, device=dev)
+    t1 = time.perf_counter()
+    M.autotune(phys)
+    log(f"autotune {time.perf_counter() - t1:.1f} s")
+    for _ in range(args.warmup):
+        M.rk3_step(phys, W, t, cfl=0.5)
+    torch.cuda.synchronize()
+    M.check()
+    M.profile(enable=1)
+    torch.cuda.synchronize()
+    s0 = time.perf_counter()
+    for k in range(args.steps):
+        M.rk3_step(phys, W, t, cfl=0.5)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - s0
+    (rms, fms), (rn, fn) = M.profile(enable=0)
+    M.check()
+    log(f"timed {args.steps} steps in {el:.3f} s; recon {rms / max(rn, 1):.3f} ms x {rn}, "
+        f"flux {fms / max(fn, 1):.3f} ms x {fn}")
+
+    N, Nq = M.n_cells, M.n_quads
+    p = 4 if prec == uw.UW_FP32 else 8
+    value = N * 3 * args.steps / el
+    rbytes = Nq * recon_bytes(4, p, nvar) + (N - Nq) * recon_bytes(3, p, nvar)
+    ravg = rms / max(rn, 1) / 1e3
+    achieved = rbytes / ravg / 1e9
+    sbytes = Nq * stage_bytes(4, p, nvar) + (N - Nq) * stage_bytes(3, p, nvar)
+
+    err = None
+    if not args.no_check and prec == uw.UW_FP32:
+        # the same steps in FP64 on the device: the FP32 result's error
+        W64 = torch.from_numpy(W0i).to(dev)
+        t64 = torch.zeros(1, dtype=torch.float64, device=dev)
+        ph64 = uw.make_physics(eq, 1.0, 1.0, 1.4, uw.UW_FP64)
+        for _ in range(args.warmup + args.steps):
+            M.rk3_step(ph64, W64, t64, cfl=0.5)
+        torch.cuda.synchronize()
+        a = W.cpu().numpy()
+        b = W64.cpu().numpy()
+        err = float((np.abs(a - b).sum(1) / np.abs(b).sum(1)).max())
+        log(f"fp32 vs fp64 relative L1 after {args.warmup + args.steps} steps: {err:.3e}")
+        del W64
+
+    base = None
+    if not args.no_cpu_baseline:
+        t1 = time.perf_counter()
+        base = cpu_baseline()
+        log(f"cpu baseline {base['value']:.3g} cell-stage/s ({time.perf_counter() - t1:.1f} s)")
+
+    out = {
+        "metric": "cell-stage updates/s, FP32 vs FP64 at L1 err<=1e-5; % of HBM roofline",
+        "value": value,
+        "unit": "cell-stage updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": el / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32" if prec == uw.UW_FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": desc, "cells": N, "quads": Nq, "triangles": N - Nq,
+                   "state": "f64", "rk3_steps": args.steps, "cfl": 0.5},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
+                     "kernel": "reconstruction (k_recon_weno, both cell types)",
+                     "bytes_per_launch": rbytes, "avg_launch_ms": ravg * 1e3},
+        "stage": {"algorithmic_bytes": sbytes, "ms": el / args.steps / 3 * 1e3,
+                  "achieved_GBs": sbytes / (el / args.steps / 3) / 1e9,
+                  "recon_ms": ravg * 1e3, "flux_ms": fms / max(fn, 1)},
+        "fp32_vs_fp64_rel_l1": err,
+        "cpu_baseline": base,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,207 @@
+/*
+ * uweno — third-order WENO finite-volume residual on unstructured
+ * quadrilateral, triangular and mixed meshes, for MI355X (gfx950).
+ *
+ * Method: Zhao, Pan, Wang, "A third-order WENO scheme on unstructured
+ * quadrilateral and triangular meshes" (arXiv:1712.08317).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every call returns uw_status; UW_OK == 0.  No C++ exception crosses the
+ *   ABI.  On failure uw_last_error() returns a message for the calling
+ *   thread, valid until that thread's next uw_* call.
+ * - Cell numbering: uw_mesh_upload renumbers cells (quadrilaterals first,
+ *   then triangles, each group along an order-16 Hilbert curve through the
+ *   cells' vertex averages, ties by original id).  All device state arrays
+ *   use this internal numbering; uw_mesh_info exports the permutation.
+ * - State layout: device, structure of arrays W[v * n_cells + i], v the
+ *   conserved variable (advection: 1 variable u; Euler: rho, rho u, rho v,
+ *   rho E as in Sec. 2 of the paper), FP64, owned by the caller.
+ * - Streams: `stream` is a hipStream_t passed as void* (NULL = the null
+ *   stream).  Device work is enqueued asynchronously; device-side failures
+ *   (non-finite values, non-positive density or pressure) are reported by
+ *   uw_check, which synchronises the stream.
+ * - Ownership: host inputs are borrowed for the duration of the call and
+ *   copied; device tables belong to the mesh until uw_mesh_destroy.
+ */
+#ifndef UWENO_H
+#define UWENO_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  UW_OK = 0,
+  UW_EINVAL = 1,      /* null pointer, bad size or enum value                    */
+  UW_EMESH = 2,       /* invalid mesh (see uw_mesh_upload)                       */
+  UW_ESTATE = 3,      /* call out of order (e.g. residual before precompute)     */
+  UW_ENOMEM = 4,      /* host or device allocation failed                        */
+  UW_EDEVICE = 5,     /* HIP error; the message names the call                   */
+  UW_ENONFINITE = 6   /* device flagged NaN/Inf or rho <= 0 / p <= 0             */
+} uw_status;
+
+enum { UW_BC_PERIODIC = 0, UW_BC_TRANSMISSIVE = 1 };
+enum { UW_WENO = 0, UW_LINEAR = 1 };
+enum { UW_D_PER_GP = 0, UW_D_PER_CELL = 1 };
+enum { UW_ADVECTION = 0, UW_EULER = 1 };
+enum { UW_FP64 = 0, UW_FP32 = 1 };   /* UW_FP32: FP32 arithmetic, FP64 state */
+
+typedef struct uw_mesh uw_mesh;
+typedef struct uw_batch uw_batch;
+
+/* Mesh description (host memory, borrowed for the call).
+ * node_xy     [n_nodes][2] coordinates.
+ * cell_nodes  [n_cells][4] counter-clockwise node indices; a triangle puts -1
+ *             in slot 3.
+ * node_id     [n_nodes] canonical node ids identifying periodic seam
+ *             duplicates (duplicates sit exactly one period apart); NULL
+ *             means every node is its own id.
+ * bc          what an unmatched face is: UW_BC_TRANSMISSIVE (a mirrored ghost
+ *             cell carrying the interior value), or UW_BC_PERIODIC (no
+ *             unmatched face allowed). */
+typedef struct {
+  int64_t n_nodes;
+  const double* node_xy;
+  int64_t n_cells;
+  const int32_t* cell_nodes;
+  const int32_t* node_id;
+  int32_t bc;
+} uw_mesh_desc;
+
+/* Scheme constants (paper Sec. 3): zeta of eq. (quadratic-2) (1e-14), theta
+ * of the weight split of Sec. 3.4 (3), eps of the nonlinear weights (not
+ * given by the paper; 1e-3), optimize = apply the linear-weight optimisation
+ * of Sec. 3.3 (1), d_scope = UW_D_PER_GP (weights d from each Gauss point's
+ * own linear weights) or UW_D_PER_CELL, mode = UW_WENO or UW_LINEAR (the
+ * quadratic P^2 of eq. (polynomial-eta) at the Gauss points). */
+typedef struct {
+  double zeta, theta, eps;
+  int32_t optimize, d_scope, mode;
+} uw_scheme;
+
+/* Physics: equation = UW_ADVECTION (u_t + ax u_x + ay u_y = 0, upwind flux)
+ * or UW_EULER (2D Euler, eq. (hyperbolic), HLLC flux, ratio `gamma`);
+ * precision = UW_FP64 or UW_FP32. */
+typedef struct {
+  int32_t equation;
+  double ax, ay, gamma;
+  int32_t precision;
+} uw_physics;
+
+/* Precompute diagnostics (Sec. 3.3): largest |gamma| before/after the
+ * optimisation, largest ||B gamma - eta||_inf and |sum gamma - 1| of the
+ * optimised weights, number of absent stencil slots (E_j = 0), number of
+ * cells whose big-stencil matrix A has rank < 5. */
+typedef struct {
+  double max_abs_gamma_raw, max_abs_gamma_opt, resid_opt, sum_dev;
+  int64_t n_absent_slots, n_rank_deficient;
+} uw_diag;
+
+const char* uw_last_error(void);
+
+/* Validates the mesh, builds face connectivity (periodic shifts, boundary
+ * faces), the Hilbert renumbering and the big stencils (Sec. 3.1 quad
+ * selection with substitutions i_j -> i_0, i_j -> i_{j-4}; Sec. 3.2
+ * triangle selection with i_j -> i_0, i_j -> i_{j-3}), and binds the mesh
+ * to HIP device `device`.  device = -1 builds a host-only mesh: connectivity,
+ * stencils and the FP64 precompute can be inspected (uw_mesh_export,
+ * uw_mesh_table) but every device call returns UW_ESTATE.
+ * Errors: UW_EINVAL (null pointers, sizes < 1), UW_EMESH (a cell whose node
+ * list is not 3 or 4 valid distinct nodes, signed area <= 0, an edge with
+ * more than two owners or traversed twice in the same direction, an
+ * unmatched face on a periodic mesh), UW_EDEVICE, UW_ENOMEM. */
+uw_status uw_mesh_upload(const uw_mesh_desc* desc, int device, uw_mesh** out);
+
+/* Sizes and the permutation.  new_of_old (nullable, host [n_cells]) receives
+ * the internal index of every original cell. */
+uw_status uw_mesh_info(const uw_mesh* mesh, int64_t* n_cells, int64_t* n_quads,
+                       int64_t* n_interior_faces, int32_t* new_of_old);
+
+/* Host export of the integer tables, internal numbering, for inspection.
+ * slots   [n_cells][13]: the cell read by stencil slot j (after substitution;
+ *         a ghost reads the cell itself; triangles use slots 0..9).
+ * present [n_cells][13]: E_j.
+ * nbr     [n_cells][4]: face neighbour (-1 boundary or unused slot).
+ * Any pointer may be NULL. */
+uw_status uw_mesh_export(const uw_mesh* mesh, int32_t* slots, uint8_t* present, int32_t* nbr);
+
+/* FP64 precompute (Sec. 3.1-3.3): scaled-frame geometry, the regularised
+ * least squares of eq. (quadratic-2) for eta (eq. (polynomial-eta)), the
+ * candidate operators, B and the linear weights of eq.
+ * (linearweight-matrix), the optimisation of Sec. 3.3; uploads the
+ * per-precision device tables on first use.  `diag` is nullable.
+ * Errors: UW_ESTATE (mesh not uploaded), UW_EINVAL, UW_ENOMEM, UW_EDEVICE. */
+uw_status uw_precompute_geometry(uw_mesh* mesh, const uw_scheme* scheme, uw_diag* diag);
+
+/* Host export of one FP64 table for inspection (internal numbering).
+ * which: 0 = gamma [n][8][12], 1 = eta [n][8][13], 2 = candidate operators
+ * Y [n][12][4], 3 = Gauss-point offsets [n][8][2], 4 = face normals and
+ * scale [n][4][3] (nx, ny, |l|/(2|Omega|)), 5 = gamma before optimisation
+ * [n][8][12].  Unused entries (triangles) are 0. */
+uw_status uw_mesh_table(const uw_mesh* mesh, int32_t which, double* out);
+
+/* L(W) of eq. (semidiscrete): L[v*n + i] = -(1/|Omega_i|) sum_p |l_p| sum_k
+ * (1/2) F(x_pk).n_p, with WENO (or linear) face states at the Gauss points
+ * of eq. (quadrature).  W, L: device FP64 [V][n_cells] (internal order).
+ * Errors: UW_ESTATE (no precompute), UW_EINVAL, UW_EDEVICE. */
+uw_status uw_residual(uw_mesh* mesh, const uw_physics* physics, const double* W, double* L,
+                      void* stream);
+
+/* One step of the three-stage TVD Runge-Kutta scheme (Sec. 4), in place on
+ * W.  t_dev: device double holding the time; dt = min(dt_fixed, t_end - t)
+ * if dt_fixed > 0, else min(cfl * min_i 2|Omega_i| / sum_p |l_p|(|u.n_p| + c),
+ * t_end - t); t_dev is advanced by dt on the device.  No host sync. */
+uw_status uw_rk3_step(uw_mesh* mesh, const uw_physics* physics, double* W, double cfl,
+                      double dt_fixed, double t_end, double* t_dev, void* stream);
+
+/* The CFL time step alone: dt_dev (device double) = cfl * min_i
+ * 2|Omega_i| / sum_p |l_p| (|u_i.n_p| + c_i), from cell averages W. */
+uw_status uw_cfl_dt(uw_mesh* mesh, const uw_physics* physics, const double* W, double cfl,
+                    double* dt_dev, void* stream);
+
+/* Many independent meshes advanced together (one launch per RK stage for
+ * all of them).  Every mesh must be precomputed with the same scheme; the
+ * batch keeps pointers to them (they must outlive it).  W_concat: device
+ * FP64, the meshes' states concatenated in order, each [V][n_k].
+ * cell_offsets: host [n+1], the start of each mesh's block in W_concat
+ * (counted in cells; the block of mesh k holds V * n_k doubles). */
+uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* physics,
+                          uw_batch** out);
+uw_status uw_batch_offsets(const uw_batch* batch, int64_t* cell_offsets);
+/* n_steps RK3 steps of every instance, each with its own CFL time step
+ * (cfl > 0) or dt_fixed (> 0), both clamped to t_end - t_k; t_dev: device
+ * [n] times. */
+uw_status uw_batch_rk3_step(uw_batch* batch, double* W_concat, double cfl, double dt_fixed,
+                            double t_end, int32_t n_steps, double* t_dev, void* stream);
+
+/* Chooses launch parameters (threads per block and cells per block of the
+ * reconstruction kernel) by timing candidates on the mesh (or batch) and
+ * stores them in it; `cache_path` (nullable) is a text file of earlier
+ * choices keyed by workload shape, read and updated. */
+uw_status uw_autotune(uw_mesh* mesh, uw_batch* batch, const uw_physics* physics,
+                      const char* cache_path, void* stream);
+
+/* Launch timing (tracing): with enable = 1 every later reconstruction and
+ * flux launch of this mesh is bracketed by HIP events on the caller's
+ * stream.  ms[0], ms[1] (nullable, host) receive the summed milliseconds of
+ * the reconstruction and flux launches recorded so far and count[0..1] their
+ * numbers; the records are then cleared.  enable = 0 stops recording,
+ * enable = -1 leaves the setting unchanged.  Synchronises on the recorded
+ * events when ms or count is given. */
+uw_status uw_profile(uw_mesh* mesh, int32_t enable, double* ms, int64_t* count);
+
+/* Synchronises `stream` and reports the device error flag of the mesh or
+ * batch (UW_ENONFINITE), clearing it. */
+uw_status uw_check(uw_mesh* mesh, uw_batch* batch, void* stream);
+
+void uw_mesh_destroy(uw_mesh* mesh);
+void uw_batch_destroy(uw_batch* batch);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* UWENO_H */

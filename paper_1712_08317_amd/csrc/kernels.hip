@@ -1,0 +1,472 @@
+// HIP kernels of the per-stage operator (gfx950).
+//
+// Paper: Sec. 3.4 (split of the linear weights, new smoothness indicator,
+// nonlinear weights, split reconstruction), Sec. 2 (Gauss-point fluxes of
+// eq. (quadrature), rotation of eq. (transform), HLLC, the residual of eq.
+// (semidiscrete)), Sec. 4 (three-stage TVD Runge-Kutta).
+//
+// One thread per cell.  The reconstruction kernel reads the cell averages of
+// the big stencil, forms the candidate gradients g_j = Y_j (dW_a, dW_b) and
+// smoothness indicators beta_j = |g_j|^2 once per cell, then for every
+// Gauss point splits the linear weights, forms the nonlinear weights and
+// writes R(x_G) = W_i0 + sigma+ sum(a+ d)/sum(a+) - sigma- sum(a- d)/sum(a-),
+// d_j = P_j(x_G) - W_i0.  Differences W_ij - W_i0 are formed in FP64 before
+// any conversion to the compute precision.
+//
+// The flux kernel evaluates each face flux in a canonical orientation (left
+// state = the cell with the lower original id, normal = that cell's outer
+// normal), so the two cells of a face compute bit-identical fluxes and the
+// gather is cell-centric, without atomics.
+#include <hip/hip_runtime.h>
+
+#include <type_traits>
+
+#include "uw_device.h"
+
+namespace uw {
+namespace {
+
+template <int NF>
+struct Layout;
+template <>
+struct Layout<4> {
+  static constexpr int S = 13, M = 12;
+  __device__ static constexpr int a(int j) {
+    constexpr int t[12] = {1, 2, 3, 4, 1, 1, 3, 3, 4, 2, 2, 4};
+    return t[j];
+  }
+  __device__ static constexpr int b(int j) {
+    constexpr int t[12] = {2, 3, 4, 1, 5, 6, 7, 8, 9, 10, 11, 12};
+    return t[j];
+  }
+};
+template <>
+struct Layout<3> {
+  static constexpr int S = 10, M = 9;
+  __device__ static constexpr int a(int j) {
+    constexpr int t[9] = {1, 2, 3, 1, 2, 3, 3, 1, 2};
+    return t[j];
+  }
+  __device__ static constexpr int b(int j) {
+    constexpr int t[9] = {2, 3, 1, 4, 5, 6, 7, 8, 9};
+    return t[j];
+  }
+};
+
+template <typename T>
+__device__ inline T rcp(T x) {
+  return T(1) / x;
+}
+
+template <typename T, int NF, int V>
+__global__ __launch_bounds__(256) void k_recon_weno(const double* __restrict__ W, int64_t N,
+                                                    TypeDev<T> td, T* __restrict__ FS, T eps,
+                                                    T theta) {
+  using L = Layout<NF>;
+  constexpr int S = L::S, M = L::M, G = 2 * NF;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= td.Nt) return;
+  const int64_t n = td.Nt, i = td.first + r;
+  double w0[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) w0[v] = W[v * N + i];
+  T dW[S - 1][V];
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s) {
+    const int64_t id = td.sid[s * n + r];
+#pragma unroll
+    for (int v = 0; v < V; ++v) dW[s][v] = (T)(W[v * N + id] - w0[v]);
+  }
+  T gx[M][V], gy[M][V], be[M][V];
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    const T y00 = td.Y[(j * 4 + 0) * n + r], y01 = td.Y[(j * 4 + 1) * n + r];
+    const T y10 = td.Y[(j * 4 + 2) * n + r], y11 = td.Y[(j * 4 + 3) * n + r];
+    const int a = L::a(j) - 1, b = L::b(j) - 1;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      gx[j][v] = y00 * dW[a][v] + y01 * dW[b][v];
+      gy[j][v] = y10 * dW[a][v] + y11 * dW[b][v];
+      be[j][v] = gx[j][v] * gx[j][v] + gy[j][v] * gy[j][v];
+    }
+  }
+#pragma unroll 1
+  for (int g = 0; g < G; ++g) {
+    const T ox = td.off[(2 * g) * n + r], oy = td.off[(2 * g + 1) * n + r];
+    T gp[M], gm[M];
+    T sp = 0, sm = 0;
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      const T ga = td.gam[(g * M + j) * n + r];
+      const T tp = T(0.5) * (ga + theta * fabs(ga));
+      const T tm = tp - ga;
+      gp[j] = tp;
+      gm[j] = tm;
+      sp += tp;
+      sm += tm;
+    }
+    const T rp = rcp(sp), rm = rcp(sm);
+#pragma unroll
+    for (int j = 0; j < M; ++j) {
+      gp[j] *= rp;
+      gm[j] *= rm;
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      T Np = 0, Dp = 0, Nm = 0, Dm = 0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const T d = ox * gx[j][v] + oy * gy[j][v];
+        const T b = be[j][v];
+        T t = gp[j] * b;
+        T q = b * (T(1) + t + t * t) + eps;
+        T al = gp[j] * rcp(q * q);
+        Dp += al;
+        Np += al * d;
+        t = gm[j] * b;
+        q = b * (T(1) + t + t * t) + eps;
+        al = gm[j] * rcp(q * q);
+        Dm += al;
+        Nm += al * d;
+      }
+      const T incr = sp * (Np / Dp) - sm * (Nm / Dm);
+      FS[(i * 8 + g) * V + v] = (T)w0[v] + incr;
+    }
+  }
+}
+
+template <typename T, int NF, int V>
+__global__ __launch_bounds__(256) void k_recon_linear(const double* __restrict__ W, int64_t N,
+                                                      TypeDev<T> td, T* __restrict__ FS) {
+  using L = Layout<NF>;
+  constexpr int S = L::S, G = 2 * NF;
+  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (r >= td.Nt) return;
+  const int64_t n = td.Nt, i = td.first + r;
+  double w0[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) w0[v] = W[v * N + i];
+  T dW[S - 1][V];
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s) {
+    const int64_t id = td.sid[s * n + r];
+#pragma unroll
+    for (int v = 0; v < V; ++v) dW[s][v] = (T)(W[v * N + id] - w0[v]);
+  }
+#pragma unroll 1
+  for (int g = 0; g < G; ++g) {
+    T acc[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] = 0;
+#pragma unroll
+    for (int s = 0; s < S - 1; ++s) {
+      const T e = td.eta[(g * (S - 1) + s) * n + r];
+#pragma unroll
+      for (int v = 0; v < V; ++v) acc[v] += e * dW[s][v];
+    }
+#pragma unroll
+    for (int v = 0; v < V; ++v) FS[(i * 8 + g) * V + v] = (T)w0[v] + acc[v];
+  }
+}
+
+// HLLC flux through a face with unit normal (nx, ny), left state WL, right
+// state WR: rotate into the face frame, Toro's HLLC with Davis wave speeds,
+// rotate back.
+template <typename T>
+__device__ inline void hllc(const T* WL, const T* WR, T nx, T ny, T gam, T* F) {
+  const T rL = WL[0], rR = WR[0];
+  const T irL = T(1) / rL, irR = T(1) / rR;
+  const T uL = (WL[1] * nx + WL[2] * ny) * irL, vL = (-WL[1] * ny + WL[2] * nx) * irL;
+  const T uR = (WR[1] * nx + WR[2] * ny) * irR, vR = (-WR[1] * ny + WR[2] * nx) * irR;
+  const T EL = WL[3], ER = WR[3];
+  const T pL = (gam - T(1)) * (EL - T(0.5) * rL * (uL * uL + vL * vL));
+  const T pR = (gam - T(1)) * (ER - T(0.5) * rR * (uR * uR + vR * vR));
+  const T aL = sqrt(gam * pL * irL), aR = sqrt(gam * pR * irR);
+  const T SL = fmin(uL - aL, uR - aR), SR = fmax(uL + aL, uR + aR);
+  const T Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
+               (rL * (SL - uL) - rR * (SR - uR));
+  T f[4];
+  if (T(0) <= SL) {
+    f[0] = rL * uL;
+    f[1] = rL * uL * uL + pL;
+    f[2] = rL * uL * vL;
+    f[3] = (EL + pL) * uL;
+  } else if (T(0) <= Ss) {
+    const T c = rL * (SL - uL) / (SL - Ss);
+    const T e = c * (EL * irL + (Ss - uL) * (Ss + pL / (rL * (SL - uL))));
+    f[0] = rL * uL + SL * (c - rL);
+    f[1] = rL * uL * uL + pL + SL * (c * Ss - rL * uL);
+    f[2] = rL * uL * vL + SL * (c * vL - rL * vL);
+    f[3] = (EL + pL) * uL + SL * (e - EL);
+  } else if (T(0) < SR) {
+    const T c = rR * (SR - uR) / (SR - Ss);
+    const T e = c * (ER * irR + (Ss - uR) * (Ss + pR / (rR * (SR - uR))));
+    f[0] = rR * uR + SR * (c - rR);
+    f[1] = rR * uR * uR + pR + SR * (c * Ss - rR * uR);
+    f[2] = rR * uR * vR + SR * (c * vR - rR * vR);
+    f[3] = (ER + pR) * uR + SR * (e - ER);
+  } else {
+    f[0] = rR * uR;
+    f[1] = rR * uR * uR + pR;
+    f[2] = rR * uR * vR;
+    f[3] = (ER + pR) * uR;
+  }
+  F[0] = f[0];
+  F[1] = f[1] * nx - f[2] * ny;
+  F[2] = f[1] * ny + f[2] * nx;
+  F[3] = f[3];
+}
+
+template <typename T, int V>
+__device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const PhysDev& p, T* F) {
+  if constexpr (V == 4) {
+    hllc<T>(WL, WR, nx, ny, (T)p.gamma, F);
+  } else {
+    const T an = (T)p.ax * nx + (T)p.ay * ny;
+    F[0] = an >= T(0) ? an * WL[0] : an * WR[0];
+  }
+}
+
+template <typename T, int V, int MODE>
+__global__ __launch_bounds__(256) void k_flux(MeshDev<T> m, PhysDev p, const T* __restrict__ FS,
+                                              const double* W_in, const double* Wn,
+                                              double* W_out,
+                                              const double* __restrict__ dtp, double* tp,
+                                              int* flag) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t N = m.N;
+  if (i >= N) return;
+  const int nf = i < m.Nq ? 4 : 3;
+  T acc[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) acc[v] = 0;
+  bool bad = false;
+  for (int k = 0; k < nf; ++k) {
+    const int32_t pk = m.fnb[k * N + i];
+    const T nx = m.fgeo[(k * 3 + 0) * N + i];
+    const T ny = m.fgeo[(k * 3 + 1) * N + i];
+    const T coef = m.fgeo[(k * 3 + 2) * N + i];
+    T o0[V], o1[V], t0[V], t1[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      o0[v] = FS[(i * 8 + 2 * k) * V + v];
+      o1[v] = FS[(i * 8 + 2 * k + 1) * V + v];
+    }
+    bool left = true;
+    if (pk < 0) {
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        t0[v] = o0[v];
+        t1[v] = o1[v];
+      }
+    } else {
+      const int64_t c = pk >> 3;
+      const int kp = (pk >> 1) & 3;
+      left = (pk & 1) != 0;
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        t0[v] = FS[(c * 8 + 2 * kp + 1) * V + v];
+        t1[v] = FS[(c * 8 + 2 * kp) * V + v];
+      }
+    }
+    if constexpr (V == 4) bad |= !(o0[0] > T(0)) || !(o1[0] > T(0));
+    T F0[V], F1[V];
+    if (left) {
+      face_flux<T, V>(o0, t0, nx, ny, p, F0);
+      face_flux<T, V>(o1, t1, nx, ny, p, F1);
+    } else {
+      face_flux<T, V>(t0, o0, nx, ny, p, F0);
+      face_flux<T, V>(t1, o1, nx, ny, p, F1);
+    }
+    const T sc = left ? coef : -coef;
+#pragma unroll
+    for (int v = 0; v < V; ++v) acc[v] += sc * (F0[v] + F1[v]);
+  }
+  double dt = 0.0;
+  if (MODE != 0) dt = *dtp;
+#pragma unroll
+  for (int v = 0; v < V; ++v) {
+    const double Lv = -(double)acc[v];
+    double out;
+    if (MODE == 0) {
+      out = Lv;
+    } else if (MODE == 1) {
+      out = W_in[v * N + i] + dt * Lv;
+    } else if (MODE == 2) {
+      out = 0.75 * Wn[v * N + i] + 0.25 * (W_in[v * N + i] + dt * Lv);
+    } else {
+      out = Wn[v * N + i] / 3.0 + 2.0 / 3.0 * (W_in[v * N + i] + dt * Lv);
+    }
+    bad |= !isfinite(out);
+    W_out[v * N + i] = out;
+  }
+  if (bad && flag) *flag = 1;
+  if (MODE == 3 && i == 0 && tp) *tp = *tp + dt;
+}
+
+__device__ inline double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+template <typename T, int V>
+__global__ __launch_bounds__(kCflBlock) void k_cfl(MeshDev<T> m, PhysDev p,
+                                                   const double* __restrict__ W,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[kCflBlock / 64];
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  const int64_t N = m.N;
+  double x = INFINITY;
+  if (i < N) {
+    double u, v, c;
+    if (V == 4) {
+      const double rho = W[i], mu = W[N + i], mv = W[2 * N + i], E = W[3 * N + i];
+      u = mu / rho;
+      v = mv / rho;
+      const double pr = (p.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+      c = sqrt(p.gamma * pr / rho);
+    } else {
+      u = p.ax;
+      v = p.ay;
+      c = 0.0;
+    }
+    const int nf = i < m.Nq ? 4 : 3;
+    double s = 0.0;
+    for (int k = 0; k < nf; ++k) {
+      const double nx = m.fgeo[(k * 3 + 0) * N + i], ny = m.fgeo[(k * 3 + 1) * N + i];
+      const double coef = m.fgeo[(k * 3 + 2) * N + i];
+      s += coef * (fabs(u * nx + v * ny) + c);
+    }
+    x = 1.0 / s;
+  }
+  x = wave_min(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < kCflBlock / 64; ++w) b = fmin(b, red[w]);
+    partial[blockIdx.x] = b;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_cfl_final(const double* __restrict__ partial,
+                                                    int64_t np, double cfl, double dt_fixed,
+                                                    double t_end, const double* t, double* dt) {
+  __shared__ double red[16];
+  double x = INFINITY;
+  if (dt_fixed <= 0.0)
+    for (int64_t k = threadIdx.x; k < np; k += blockDim.x) x = fmin(x, partial[k]);
+  x = wave_min(x);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  if (lane == 0) red[wid] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double b = red[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmin(b, red[w]);
+    double d = dt_fixed > 0.0 ? dt_fixed : cfl * b;
+    const double rest = t_end - (t ? *t : 0.0);
+    d = fmin(d, rest);
+    *dt = d > 0.0 ? d : 0.0;
+  }
+}
+
+template <typename F>
+hipError_t grid_launch(int64_t n, int block, F&& f) {
+  if (n <= 0) return hipSuccess;
+  const int64_t grid = (n + block - 1) / block;
+  f((unsigned)grid);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, int nvar, const double* W, T* FS,
+                        int block, hipStream_t st) {
+  hipError_t e = hipSuccess;
+  const bool lin = s.mode == 1;
+  const T eps = (T)s.eps, th = (T)s.theta;
+  auto one = [&](const TypeDev<T>& td, auto nf_tag) {
+    constexpr int NF = decltype(nf_tag)::value;
+    return grid_launch(td.Nt, block, [&](unsigned grid) {
+      if (lin) {
+        if (nvar == 4)
+          k_recon_linear<T, NF, 4><<<grid, block, 0, st>>>(W, m.N, td, FS);
+        else
+          k_recon_linear<T, NF, 1><<<grid, block, 0, st>>>(W, m.N, td, FS);
+      } else {
+        if (nvar == 4)
+          k_recon_weno<T, NF, 4><<<grid, block, 0, st>>>(W, m.N, td, FS, eps, th);
+        else
+          k_recon_weno<T, NF, 1><<<grid, block, 0, st>>>(W, m.N, td, FS, eps, th);
+      }
+    });
+  };
+  e = one(m.quad, std::integral_constant<int, 4>{});
+  if (e != hipSuccess) return e;
+  return one(m.tri, std::integral_constant<int, 3>{});
+}
+
+template <typename T>
+hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, int nvar, int mode, const T* FS,
+                       const double* W_in, const double* Wn, double* W_out, const double* dt,
+                       double* t, int* flag, int block, hipStream_t st) {
+  return grid_launch(m.N, block, [&](unsigned grid) {
+#define UW_FLUX(V, MODE) \
+  k_flux<T, V, MODE><<<grid, block, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, t, flag)
+    if (nvar == 4) {
+      switch (mode) {
+        case 0: UW_FLUX(4, 0); break;
+        case 1: UW_FLUX(4, 1); break;
+        case 2: UW_FLUX(4, 2); break;
+        default: UW_FLUX(4, 3); break;
+      }
+    } else {
+      switch (mode) {
+        case 0: UW_FLUX(1, 0); break;
+        case 1: UW_FLUX(1, 1); break;
+        case 2: UW_FLUX(1, 2); break;
+        default: UW_FLUX(1, 3); break;
+      }
+    }
+#undef UW_FLUX
+  });
+}
+
+template <typename T>
+hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const double* W, double cfl,
+                      double dt_fixed, double t_end, const double* t, double* partial,
+                      double* dt, hipStream_t st) {
+  const int64_t np = cfl_partials(m.N);
+  if (dt_fixed <= 0.0) {
+    if (nvar == 4)
+      k_cfl<T, 4><<<(unsigned)np, kCflBlock, 0, st>>>(m, p, W, partial);
+    else
+      k_cfl<T, 1><<<(unsigned)np, kCflBlock, 0, st>>>(m, p, W, partial);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  k_cfl_final<<<1, 1024, 0, st>>>(partial, np, cfl, dt_fixed, t_end, t, dt);
+  return hipGetLastError();
+}
+
+template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, int,
+                                         const double*, double*, int, hipStream_t);
+template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, int,
+                                        const double*, float*, int, hipStream_t);
+template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, int, int,
+                                        const double*, const double*, const double*, double*,
+                                        const double*, double*, int*, int, hipStream_t);
+template hipError_t launch_flux<float>(const MeshDev<float>&, const PhysDev&, int, int,
+                                       const float*, const double*, const double*, double*,
+                                       const double*, double*, int*, int, hipStream_t);
+template hipError_t launch_cfl<double>(const MeshDev<double>&, const PhysDev&, int, const double*,
+                                       double, double, double, const double*, double*, double*,
+                                       hipStream_t);
+template hipError_t launch_cfl<float>(const MeshDev<float>&, const PhysDev&, int, const double*,
+                                      double, double, double, const double*, double*, double*,
+                                      hipStream_t);
+
+}  // namespace uw

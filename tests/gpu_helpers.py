@@ -1,0 +1,42 @@
+"""Shared helpers of the GPU tests and the benchmark: run the HIP path and
+the oracle on the same seeded inputs and compare them."""
+from __future__ import annotations
+
+import numpy as np
+
+import workloads as wl
+
+
+def rel_l1(a, b):
+    """Largest over variables of sum|a - b| / sum|b|."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    num = np.abs(a - b).sum(axis=-1)
+    den = np.maximum(np.abs(b).sum(axis=-1), 1e-300)
+    return float((num / den).max())
+
+
+def physics_for(uw, equation, precision):
+    eq = uw.UW_EULER if equation == "euler" else uw.UW_ADVECTION
+    pr = uw.UW_FP64 if precision == "fp64" else uw.UW_FP32
+    return uw.make_physics(eq, 1.0, 1.0, 1.4, pr)
+
+
+def gpu_residual(uw, M, W_orig, equation, precision, device="cuda:0"):
+    """L(W) from the HIP library, returned in the original cell order."""
+    import torch
+    Wi = torch.from_numpy(M.to_internal(W_orig)).to(device)
+    L = torch.empty_like(Wi)
+    M.residual(physics_for(uw, equation, precision), Wi, L)
+    torch.cuda.synchronize()
+    return M.to_original(L.cpu().numpy())
+
+
+def small_meshes():
+    return {
+        "c1": wl.mesh_c1(),
+        "quad": wl.grid_mesh(24, 24, 2.0, 2.0, "quad", 0.2, 2, True),
+        "tri": wl.grid_mesh(17, 17, 2.0, 2.0, "tri", 0.2, 3, True),
+        "mixed": wl.mesh_c5(n=32, block=8, jitter=0.3, seed=6),
+        "sod": wl.mesh_c3(n=40, jitter=0.15, seed=4, band=0.1),
+    }

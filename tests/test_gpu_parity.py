@@ -1,0 +1,180 @@
+"""Parity of the HIP path with the oracle (element by element, same seeded
+inputs).  Bars: FP64 relative L1 <= 1e-12, FP32 (FP64 state) <= 1e-5."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import weights as ow
+from oracle import scheme as osc
+from gpu_helpers import rel_l1, gpu_residual, physics_for, small_meshes
+
+pytestmark = pytest.mark.gpu
+
+MESHES = small_meshes()
+_cache = {}
+
+
+def _setup(name, mode="weno"):
+    key = (name, mode)
+    if key not in _cache:
+        import paper_1712_08317_amd as uw
+        mesh = MESHES[name]
+        M = uw.Mesh.from_workload(mesh, device=0)
+        M.precompute(uw.make_scheme(mode=uw.UW_LINEAR if mode == "linear" else uw.UW_WENO))
+        T = ow.precompute(mesh, ow.Scheme(mode=mode))
+        _cache[key] = (uw, mesh, M, T)
+    return _cache[key]
+
+
+def _state(name, mesh, seed):
+    if name == "c1":
+        return wl.seeded_state(mesh, 1, seed)
+    if name == "sod":
+        return wl.initial_state("c3", mesh)
+    return wl.seeded_state(mesh, 4, seed)
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("mode", ["weno", "linear"])
+def test_residual_fp64(name, mode):
+    uw, mesh, M, T = _setup(name, mode)
+    eq = "advection" if name == "c1" else "euler"
+    W = _state(name, mesh, 11)
+    ref = osc.residual_vectorized(T, W, osc.Physics(eq))
+    got = gpu_residual(uw, M, W, eq, "fp64")
+    print(name, mode, "rel L1", rel_l1(got, ref))
+    assert rel_l1(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_residual_fp32(name):
+    uw, mesh, M, T = _setup(name)
+    eq = "advection" if name == "c1" else "euler"
+    W = _state(name, mesh, 12)
+    ref = osc.residual_vectorized(T, W, osc.Physics(eq))
+    got = gpu_residual(uw, M, W, eq, "fp32")
+    print(name, "fp32 rel L1", rel_l1(got, ref))
+    assert rel_l1(got, ref) <= 1e-5
+
+
+def test_uniform_state_and_conservation():
+    import torch
+    uw, mesh, M, T = _setup("mixed")
+    W = np.tile(np.array([[1.3], [0.2], [-0.7], [4.1]]), (1, mesh.n_cells))
+    for prec in ("fp64", "fp32"):
+        L = gpu_residual(uw, M, W, "euler", prec)
+        assert np.abs(L).max() < (1e-11 if prec == "fp64" else 2e-4)
+    Ws = wl.seeded_state(mesh, 4, 13)
+    L = gpu_residual(uw, M, Ws, "euler", "fp64")
+    area = np.zeros(mesh.n_cells)
+    for g in T.groups.values():
+        area[g.st.cells] = g.area
+    tot = np.abs((L * area).sum(axis=1))
+    assert (tot < 1e-12 * np.abs(L * area).sum(axis=1)).all()
+    del torch
+
+
+def test_bitwise_reproducible():
+    import torch
+    uw, mesh, M, T = _setup("mixed")
+    W = _state("mixed", mesh, 14)
+    for prec in ("fp64", "fp32"):
+        a = gpu_residual(uw, M, W, "euler", prec)
+        b = gpu_residual(uw, M, W, "euler", prec)
+        assert np.array_equal(a, b)
+    del torch
+
+
+@pytest.mark.parametrize("name", ["c1", "mixed", "sod"])
+def test_rk3_steps_fp64_match_oracle(name):
+    import torch
+    uw, mesh, M, T = _setup(name)
+    eq = "advection" if name == "c1" else "euler"
+    W = wl.initial_state("c1", mesh) if name == "c1" else _state(name, mesh, 15)
+    ph = osc.Physics(eq)
+    dt = 0.5 * osc.cfl_dt(T, W, ph, 0.5)
+    ref = W.copy()
+    for _ in range(3):
+        ref = osc.rk3_step(T, ref, ph, dt)
+    Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    for _ in range(3):
+        M.rk3_step(physics_for(uw, eq, "fp64"), Wd, t, dt_fixed=dt)
+    M.check()
+    got = M.to_original(Wd.cpu().numpy())
+    print(name, "rk3 rel L1", rel_l1(got, ref))
+    assert rel_l1(got, ref) <= 1e-12
+    assert abs(t.item() - 3 * dt) <= 1e-15
+
+
+def test_c1_to_final_time_with_device_cfl():
+    """Configuration 1: scalar advection, FP64, CFL 0.5 to t = 0.2 with the
+    time step chosen on the device; the oracle repeats the same steps."""
+    import torch
+    uw, mesh, M, T = _setup("c1")
+    W0 = wl.initial_state("c1", mesh)
+    ph = osc.Physics("advection")
+    Wd = torch.from_numpy(M.to_internal(W0)).to("cuda:0")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ref = W0.copy()
+    tr = 0.0
+    steps = 0
+    while tr < 0.2 - 1e-14 and steps < 100:
+        dt = min(osc.cfl_dt(T, ref, ph, 0.5), 0.2 - tr)
+        ref = osc.rk3_step(T, ref, ph, dt)
+        tr += dt
+        M.rk3_step(physics_for(uw, "advection", "fp64"), Wd, t, cfl=0.5, t_end=0.2)
+        steps += 1
+    torch.cuda.synchronize()
+    assert abs(t.item() - 0.2) < 1e-13
+    got = M.to_original(Wd.cpu().numpy())
+    assert rel_l1(got, ref) <= 1e-12
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_cfl_dt_matches_oracle(prec):
+    import torch
+    uw, mesh, M, T = _setup("mixed")
+    W = wl.seeded_state(mesh, 4, 16)
+    ref = osc.cfl_dt(T, W, osc.Physics("euler"), 0.5)
+    Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+    dt = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    M.cfl_dt(physics_for(uw, "euler", prec), Wd, 0.5, dt)
+    torch.cuda.synchronize()
+    assert abs(dt.item() / ref - 1) < (1e-13 if prec == "fp64" else 1e-6)
+
+
+def test_fp32_solution_within_1e5_of_fp64_oracle():
+    """FP32 arithmetic with FP64 state: after 10 steps of the smooth mixed-mesh
+    Euler problem the relative L1 error against the FP64 oracle is <= 1e-5."""
+    import torch
+    uw, mesh, M, T = _setup("mixed")
+    W0 = wl.initial_state("c5", mesh)
+    ph = osc.Physics("euler")
+    dt = osc.cfl_dt(T, W0, ph, 0.5)
+    ref = W0.copy()
+    for _ in range(10):
+        ref = osc.rk3_step(T, ref, ph, dt)
+    Wd = torch.from_numpy(M.to_internal(W0)).to("cuda:0")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    for _ in range(10):
+        M.rk3_step(physics_for(uw, "euler", "fp32"), Wd, t, dt_fixed=dt)
+    M.check()
+    got = M.to_original(Wd.cpu().numpy())
+    err = rel_l1(got, ref)
+    print("fp32 10-step rel L1", err)
+    assert err <= 1e-5
+
+
+def test_nonfinite_state_is_flagged():
+    import torch
+    uw, mesh, M, T = _setup("quad")
+    W = wl.seeded_state(mesh, 4, 17)
+    W[0, 5] = np.nan
+    Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    M.rk3_step(physics_for(uw, "euler", "fp64"), Wd, t, dt_fixed=1e-3)
+    with pytest.raises(uw.UwError) as e:
+        M.check()
+    assert e.value.status == uw.UW_ENONFINITE
+    M.check()   # the flag was cleared
