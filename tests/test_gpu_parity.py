@@ -26,10 +26,12 @@ def _setup(name, mode="weno"):
     return _cache[key]
 
 
-def _state(name, mesh, seed):
+def _state(name, mesh, seed, mode="weno"):
     if name == "c1":
         return wl.seeded_state(mesh, 1, seed)
-    if name == "sod":
+    if name == "sod" and mode == "weno":
+        # the unlimited linear scheme gives negative pressure at the shock
+        # tube's jump, so the linear mode is compared on a smooth state
         return wl.initial_state("c3", mesh)
     return wl.seeded_state(mesh, 4, seed)
 
@@ -39,8 +41,9 @@ def _state(name, mesh, seed):
 def test_residual_fp64(name, mode):
     uw, mesh, M, T = _setup(name, mode)
     eq = "advection" if name == "c1" else "euler"
-    W = _state(name, mesh, 11)
+    W = _state(name, mesh, 11, mode)
     ref = osc.residual_vectorized(T, W, osc.Physics(eq))
+    assert np.isfinite(ref).all()
     got = gpu_residual(uw, M, W, eq, "fp64")
     print(name, mode, "rel L1", rel_l1(got, ref))
     assert rel_l1(got, ref) <= 1e-12
