@@ -98,6 +98,8 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 reference run")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="run a plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-mesh path "
@@ -128,6 +130,13 @@ def main():
     phys = uw.make_physics(eq, 1.0, 1.0, 1.4, prec)
     W = torch.from_numpy(W0i).to(dev)
     t = torch.zeros(1, dtype=torch.float64, device=dev)
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device=dev).fill_(1.0)
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy probe: 1 GiB read + 1 GiB written")
+        del a, b
     t1 = time.perf_counter()
     M.autotune(phys)
     log(f"autotune {time.perf_counter() - t1:.1f} s")

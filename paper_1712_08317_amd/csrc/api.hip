@@ -13,6 +13,8 @@
 #include "uw_device.h"
 #include "uw_host.h"
 
+static_assert(uw::kTile == uw::kReconBlock, "tile size and reconstruction block differ");
+
 namespace {
 
 thread_local std::string g_err;
@@ -79,11 +81,12 @@ std::vector<T> convert(const std::vector<double>& v) {
 template <class T>
 struct DevTables {
   bool ready = false;
-  DevBuf q_sid, q_Y, q_off, q_gam, q_eta, t_sid, t_Y, t_off, t_gam, t_eta, fnb, fgeo;
+  DevBuf q_to, q_ti, q_li, q_Y, q_off, q_gam, q_eta, t_to, t_ti, t_li, t_Y, t_off, t_gam, t_eta,
+      fnb, fgeo;
   uw::MeshDev<T> view;
   void reset() {
-    for (DevBuf* b : {&q_sid, &q_Y, &q_off, &q_gam, &q_eta, &t_sid, &t_Y, &t_off, &t_gam, &t_eta,
-                      &fnb, &fgeo})
+    for (DevBuf* b : {&q_to, &q_ti, &q_li, &q_Y, &q_off, &q_gam, &q_eta, &t_to, &t_ti, &t_li,
+                      &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fgeo})
       b->release();
     view = uw::MeshDev<T>();
     ready = false;
@@ -140,25 +143,32 @@ uw_status ensure_tables(uw_mesh* m) {
   if (d.ready) return UW_OK;
   UW_HIP(hipSetDevice(m->device));
   const uw::HostTables& t = m->tables;
-  auto up_type = [&](const uw::TypeTables& tt, DevBuf& sid, DevBuf& Y, DevBuf& off, DevBuf& gam,
-                     DevBuf& eta, uw::TypeDev<T>& view) -> hipError_t {
+  auto up_type = [&](const uw::TypeTables& tt, DevBuf& to, DevBuf& ti, DevBuf& li, DevBuf& Y,
+                     DevBuf& off, DevBuf& gam, DevBuf& eta, uw::TypeDev<T>& view) -> hipError_t {
     hipError_t e;
-    if ((e = sid.upload(tt.sid)) != hipSuccess) return e;
+    if ((e = to.upload(tt.tile_off)) != hipSuccess) return e;
+    if ((e = ti.upload(tt.tile_ids)) != hipSuccess) return e;
+    if ((e = li.upload(tt.lidx)) != hipSuccess) return e;
     if ((e = Y.upload(convert<T>(tt.Y))) != hipSuccess) return e;
     if ((e = off.upload(convert<T>(tt.off))) != hipSuccess) return e;
     if ((e = gam.upload(convert<T>(tt.gam))) != hipSuccess) return e;
     if ((e = eta.upload(convert<T>(tt.eta))) != hipSuccess) return e;
     view.Nt = tt.Nt;
     view.first = tt.first;
-    view.sid = sid.template as<int32_t>();
+    view.tile_off = to.template as<int32_t>();
+    view.tile_ids = ti.template as<int32_t>();
+    view.lidx = li.template as<uint16_t>();
+    view.max_tile_len = tt.max_tile_len;
     view.Y = Y.template as<T>();
     view.off = off.template as<T>();
     view.gam = gam.template as<T>();
     view.eta = eta.template as<T>();
     return hipSuccess;
   };
-  hipError_t e = up_type(t.quad, d.q_sid, d.q_Y, d.q_off, d.q_gam, d.q_eta, d.view.quad);
-  if (e == hipSuccess) e = up_type(t.tri, d.t_sid, d.t_Y, d.t_off, d.t_gam, d.t_eta, d.view.tri);
+  hipError_t e =
+      up_type(t.quad, d.q_to, d.q_ti, d.q_li, d.q_Y, d.q_off, d.q_gam, d.q_eta, d.view.quad);
+  if (e == hipSuccess)
+    e = up_type(t.tri, d.t_to, d.t_ti, d.t_li, d.t_Y, d.t_off, d.t_gam, d.t_eta, d.view.tri);
   if (e == hipSuccess) e = d.fnb.upload(t.fnb);
   if (e == hipSuccess) e = d.fgeo.upload(convert<T>(t.fgeo));
   if (e == hipErrorOutOfMemory) return fail(UW_ENOMEM, "device tables: out of memory");
@@ -225,7 +235,7 @@ uw_status stage(uw_mesh* m, const uw_physics* p, int mode, const double* W_in, c
   T* FS = m->FS.template as<T>();
   hipEvent_t a = nullptr, b = nullptr;
   if (m->profiling) UW_HIP(ev_begin(m, st, &a, &b));
-  hipError_t e = uw::launch_recon<T>(d.view, scheme_dev(m), nvar, W_in, FS, m->block_recon, st);
+  hipError_t e = uw::launch_recon<T>(d.view, scheme_dev(m), nvar, W_in, FS, st);
   if (e != hipSuccess) return hip_fail(e, "reconstruction launch");
   if (m->profiling) {
     UW_HIP(hipEventRecord(b, st));
@@ -577,8 +587,8 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
     UW_HIP(hipEventCreate(&e0));
     UW_HIP(hipEventCreate(&e1));
     const int cands[3] = {64, 128, 256};
-    for (int which = 0; which < 2; ++which) {
-      int* knob = which == 0 ? &x->block_recon : &x->block_flux;
+    for (int which = 1; which < 2; ++which) {
+      int* knob = &x->block_flux;
       int best_c = *knob;
       float best = 1e30f;
       for (int c : cands) {

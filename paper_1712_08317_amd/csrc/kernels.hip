@@ -53,30 +53,93 @@ struct Layout<3> {
   }
 };
 
-template <typename T>
-__device__ inline T rcp(T x) {
-  return T(1) / x;
+// Reciprocal without the IEEE division sequence: v_rcp_f32 (1 ulp) in FP32;
+// in FP64 v_rcp_f64 refined by two Newton steps.
+__device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return r;
+}
+
+template <typename T, int V>
+__device__ inline void store_state(T* p, const T* x) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) p[v] = x[v];
+}
+template <>
+__device__ inline void store_state<float, 4>(float* p, const float* x) {
+  *reinterpret_cast<float4*>(p) = make_float4(x[0], x[1], x[2], x[3]);
+}
+template <>
+__device__ inline void store_state<double, 4>(double* p, const double* x) {
+  reinterpret_cast<double2*>(p)[0] = make_double2(x[0], x[1]);
+  reinterpret_cast<double2*>(p)[1] = make_double2(x[2], x[3]);
+}
+
+template <typename T, int V>
+__device__ inline void load_state(const T* p, T* x) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) x[v] = p[v];
+}
+template <>
+__device__ inline void load_state<float, 4>(const float* p, float* x) {
+  const float4 a = *reinterpret_cast<const float4*>(p);
+  x[0] = a.x;
+  x[1] = a.y;
+  x[2] = a.z;
+  x[3] = a.w;
+}
+template <>
+__device__ inline void load_state<double, 4>(const double* p, double* x) {
+  const double2 a = reinterpret_cast<const double2*>(p)[0];
+  const double2 b = reinterpret_cast<const double2*>(p)[1];
+  x[0] = a.x;
+  x[1] = a.y;
+  x[2] = b.x;
+  x[3] = b.y;
+}
+
+// Stages the cell averages read by one tile's stencils into LDS (FP64) and
+// returns the list length; every thread of the block must call it.
+template <int V>
+__device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const int32_t* tile_off,
+                                 const int32_t* __restrict__ tile_ids, double* lds) {
+  const int beg = tile_off[blockIdx.x], len = tile_off[blockIdx.x + 1] - beg;
+  for (int k = threadIdx.x; k < len; k += blockDim.x) {
+    const int64_t id = tile_ids[beg + k];
+#pragma unroll
+    for (int v = 0; v < V; ++v) lds[v * len + k] = W[v * N + id];
+  }
+  __syncthreads();
+  return len;
 }
 
 template <typename T, int NF, int V>
-__global__ __launch_bounds__(256) void k_recon_weno(const double* __restrict__ W, int64_t N,
-                                                    TypeDev<T> td, T* __restrict__ FS, T eps,
-                                                    T theta) {
+__global__ __launch_bounds__(kReconBlock, sizeof(T) == 4 ? 2 : 1) void k_recon_weno(const double* __restrict__ W,
+                                                            int64_t N, TypeDev<T> td,
+                                                            T* __restrict__ FS, T eps, T theta) {
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, G = 2 * NF;
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  extern __shared__ double lds[];
+  const int len = stage_tile<V>(W, N, td.tile_off, td.tile_ids, lds);
+  const int64_t r = (int64_t)blockIdx.x * kReconBlock + threadIdx.x;
   if (r >= td.Nt) return;
   const int64_t n = td.Nt, i = td.first + r;
   double w0[V];
+  const int l0 = td.lidx[r];
 #pragma unroll
-  for (int v = 0; v < V; ++v) w0[v] = W[v * N + i];
+  for (int v = 0; v < V; ++v) w0[v] = lds[v * len + l0];
+  // differences to the stencil cells, formed in FP64
   T dW[S - 1][V];
 #pragma unroll
   for (int s = 0; s < S - 1; ++s) {
-    const int64_t id = td.sid[s * n + r];
+    const int l = td.lidx[(s + 1) * n + r];
 #pragma unroll
-    for (int v = 0; v < V; ++v) dW[s][v] = (T)(W[v * N + id] - w0[v]);
+    for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
+  // candidate gradients g_j = Y_j (dW_a, dW_b) and indicators beta_j = |g_j|^2
   T gx[M][V], gy[M][V], be[M][V];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
@@ -93,6 +156,8 @@ __global__ __launch_bounds__(256) void k_recon_weno(const double* __restrict__ W
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
     const T ox = td.off[(2 * g) * n + r], oy = td.off[(2 * g + 1) * n + r];
+    // split of the linear weights: gamma~+ = (gamma + theta|gamma|)/2,
+    // gamma~- = gamma~+ - gamma, normalised by their sums sigma+-
     T gp[M], gm[M];
     T sp = 0, sm = 0;
 #pragma unroll
@@ -111,47 +176,55 @@ __global__ __launch_bounds__(256) void k_recon_weno(const double* __restrict__ W
       gp[j] *= rp;
       gm[j] *= rm;
     }
+    T R[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
+      // alpha = gamma / (beta (1 + gamma beta + (gamma beta)^2) + eps)^2
       T Np = 0, Dp = 0, Nm = 0, Dm = 0;
 #pragma unroll
       for (int j = 0; j < M; ++j) {
-        const T d = ox * gx[j][v] + oy * gy[j][v];
+        const T d = fma(ox, gx[j][v], oy * gy[j][v]);
         const T b = be[j][v];
+        const T be_eps = b + eps;
+        // q = beta (1 + t + t^2) + eps with t = gamma beta: q = beta u + (beta + eps), u = t + t^2
         T t = gp[j] * b;
-        T q = b * (T(1) + t + t * t) + eps;
+        T q = fma(b, fma(t, t, t), be_eps);
         T al = gp[j] * rcp(q * q);
         Dp += al;
-        Np += al * d;
+        Np = fma(al, d, Np);
         t = gm[j] * b;
-        q = b * (T(1) + t + t * t) + eps;
+        q = fma(b, fma(t, t, t), be_eps);
         al = gm[j] * rcp(q * q);
         Dm += al;
-        Nm += al * d;
+        Nm = fma(al, d, Nm);
       }
-      const T incr = sp * (Np / Dp) - sm * (Nm / Dm);
-      FS[(i * 8 + g) * V + v] = (T)w0[v] + incr;
+      R[v] = (T)w0[v] + (sp * (Np * rcp(Dp)) - sm * (Nm * rcp(Dm)));
     }
+    store_state<T, V>(FS + (i * 8 + g) * V, R);
   }
 }
 
 template <typename T, int NF, int V>
-__global__ __launch_bounds__(256) void k_recon_linear(const double* __restrict__ W, int64_t N,
-                                                      TypeDev<T> td, T* __restrict__ FS) {
+__global__ __launch_bounds__(kReconBlock) void k_recon_linear(const double* __restrict__ W,
+                                                              int64_t N, TypeDev<T> td,
+                                                              T* __restrict__ FS) {
   using L = Layout<NF>;
   constexpr int S = L::S, G = 2 * NF;
-  const int64_t r = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  extern __shared__ double lds[];
+  const int len = stage_tile<V>(W, N, td.tile_off, td.tile_ids, lds);
+  const int64_t r = (int64_t)blockIdx.x * kReconBlock + threadIdx.x;
   if (r >= td.Nt) return;
   const int64_t n = td.Nt, i = td.first + r;
   double w0[V];
+  const int l0 = td.lidx[r];
 #pragma unroll
-  for (int v = 0; v < V; ++v) w0[v] = W[v * N + i];
+  for (int v = 0; v < V; ++v) w0[v] = lds[v * len + l0];
   T dW[S - 1][V];
 #pragma unroll
   for (int s = 0; s < S - 1; ++s) {
-    const int64_t id = td.sid[s * n + r];
+    const int l = td.lidx[(s + 1) * n + r];
 #pragma unroll
-    for (int v = 0; v < V; ++v) dW[s][v] = (T)(W[v * N + id] - w0[v]);
+    for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
@@ -164,8 +237,10 @@ __global__ __launch_bounds__(256) void k_recon_linear(const double* __restrict__
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] += e * dW[s][v];
     }
+    T R[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) FS[(i * 8 + g) * V + v] = (T)w0[v] + acc[v];
+    for (int v = 0; v < V; ++v) R[v] = (T)w0[v] + acc[v];
+    store_state<T, V>(FS + (i * 8 + g) * V, R);
   }
 }
 
@@ -247,11 +322,8 @@ __global__ __launch_bounds__(256) void k_flux(MeshDev<T> m, PhysDev p, const T* 
     const T ny = m.fgeo[(k * 3 + 1) * N + i];
     const T coef = m.fgeo[(k * 3 + 2) * N + i];
     T o0[V], o1[V], t0[V], t1[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      o0[v] = FS[(i * 8 + 2 * k) * V + v];
-      o1[v] = FS[(i * 8 + 2 * k + 1) * V + v];
-    }
+    load_state<T, V>(FS + (i * 8 + 2 * k) * V, o0);
+    load_state<T, V>(FS + (i * 8 + 2 * k + 1) * V, o1);
     bool left = true;
     if (pk < 0) {
 #pragma unroll
@@ -263,11 +335,8 @@ __global__ __launch_bounds__(256) void k_flux(MeshDev<T> m, PhysDev p, const T* 
       const int64_t c = pk >> 3;
       const int kp = (pk >> 1) & 3;
       left = (pk & 1) != 0;
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        t0[v] = FS[(c * 8 + 2 * kp + 1) * V + v];
-        t1[v] = FS[(c * 8 + 2 * kp) * V + v];
-      }
+      load_state<T, V>(FS + (c * 8 + 2 * kp + 1) * V, t0);
+      load_state<T, V>(FS + (c * 8 + 2 * kp) * V, t1);
     }
     if constexpr (V == 4) bad |= !(o0[0] > T(0)) || !(o1[0] > T(0));
     T F0[V], F1[V];
@@ -384,27 +453,28 @@ hipError_t grid_launch(int64_t n, int block, F&& f) {
 
 template <typename T>
 hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, int nvar, const double* W, T* FS,
-                        int block, hipStream_t st) {
-  hipError_t e = hipSuccess;
+                        hipStream_t st) {
   const bool lin = s.mode == 1;
   const T eps = (T)s.eps, th = (T)s.theta;
-  auto one = [&](const TypeDev<T>& td, auto nf_tag) {
+  auto one = [&](const TypeDev<T>& td, auto nf_tag) -> hipError_t {
     constexpr int NF = decltype(nf_tag)::value;
-    return grid_launch(td.Nt, block, [&](unsigned grid) {
-      if (lin) {
-        if (nvar == 4)
-          k_recon_linear<T, NF, 4><<<grid, block, 0, st>>>(W, m.N, td, FS);
-        else
-          k_recon_linear<T, NF, 1><<<grid, block, 0, st>>>(W, m.N, td, FS);
-      } else {
-        if (nvar == 4)
-          k_recon_weno<T, NF, 4><<<grid, block, 0, st>>>(W, m.N, td, FS, eps, th);
-        else
-          k_recon_weno<T, NF, 1><<<grid, block, 0, st>>>(W, m.N, td, FS, eps, th);
-      }
-    });
+    if (td.Nt <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)((td.Nt + kReconBlock - 1) / kReconBlock);
+    const size_t shm = (size_t)td.max_tile_len * nvar * sizeof(double);
+    if (lin) {
+      if (nvar == 4)
+        k_recon_linear<T, NF, 4><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS);
+      else
+        k_recon_linear<T, NF, 1><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS);
+    } else {
+      if (nvar == 4)
+        k_recon_weno<T, NF, 4><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS, eps, th);
+      else
+        k_recon_weno<T, NF, 1><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS, eps, th);
+    }
+    return hipGetLastError();
   };
-  e = one(m.quad, std::integral_constant<int, 4>{});
+  hipError_t e = one(m.quad, std::integral_constant<int, 4>{});
   if (e != hipSuccess) return e;
   return one(m.tri, std::integral_constant<int, 3>{});
 }
@@ -453,9 +523,9 @@ hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const dou
 }
 
 template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, int,
-                                         const double*, double*, int, hipStream_t);
+                                         const double*, double*, hipStream_t);
 template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, int,
-                                        const double*, float*, int, hipStream_t);
+                                        const double*, float*, hipStream_t);
 template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, int, int,
                                         const double*, const double*, const double*, double*,
                                         const double*, double*, int*, int, hipStream_t);

@@ -8,10 +8,15 @@
 namespace uw {
 
 // Tables of one cell type, structure of arrays [k][Nt].
+constexpr int kReconBlock = 256;   // cells per reconstruction tile (one block)
+
 template <typename T>
 struct TypeDev {
   int64_t Nt = 0, first = 0;
-  const int32_t* sid = nullptr;   // [S-1][Nt]
+  const int32_t* tile_off = nullptr;   // [n_tiles + 1]
+  const int32_t* tile_ids = nullptr;   // cells staged in LDS by each tile
+  const uint16_t* lidx = nullptr;      // [S][Nt] LDS position of each slot (0 = self)
+  int32_t max_tile_len = 0;
   const T* Y = nullptr;           // [M*4][Nt]
   const T* off = nullptr;         // [2n*2][Nt]
   const T* gam = nullptr;         // [2n*M][Nt]
@@ -36,10 +41,11 @@ struct SchemeDev {
   int mode;       // 0 WENO, 1 linear
 };
 
-// Face states at the Gauss points: FS[(i*8 + g)*V + v].
+// Face states at the Gauss points: FS[(i*8 + g)*V + v].  One block of
+// kReconBlock threads per tile.
 template <typename T>
 hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, int nvar, const double* W, T* FS,
-                        int block, hipStream_t st);
+                        hipStream_t st);
 
 // Flux, residual gather and RK stage.  mode 0: L = L(W_in); mode 1..3: the
 // three stages of the TVD Runge-Kutta scheme, W_out from W_in, Wn and *dt.

@@ -28,6 +28,7 @@ extern const TypeConst kTri;
 inline const TypeConst& type_const(int nf) { return nf == 4 ? kQuad : kTri; }
 
 constexpr int kMaxS = 13, kMaxM = 12, kMaxG = 8;
+constexpr int kTile = 256;   // cells per reconstruction block
 
 struct Error {
   int code;
@@ -71,6 +72,12 @@ struct SchemeParams {
 struct TypeTables {
   int64_t Nt = 0, first = 0;
   std::vector<int32_t> sid;     // [S-1][Nt] cell read by slot s = 1..S-1 (after substitution)
+  // LDS staging: tiles of kTile consecutive cells; the sorted distinct cells
+  // read by a tile's stencils, and each slot's position in that list
+  std::vector<int32_t> tile_off;   // [n_tiles + 1]
+  std::vector<int32_t> tile_ids;   // [tile_off[n_tiles]]
+  std::vector<uint16_t> lidx;      // [S][Nt] (slot 0 = the cell itself)
+  int32_t max_tile_len = 0;
   std::vector<double> Y;        // [M*4][Nt] candidate operators (Y00, Y01, Y10, Y11)
   std::vector<double> off;      // [2n*2][Nt] (p^1, p^2) at each Gauss point
   std::vector<double> gam;      // [2n*M][Nt] optimised linear weights
