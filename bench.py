@@ -139,7 +139,7 @@ def main():
         del a, b
     t1 = time.perf_counter()
     M.autotune(phys)
-    log(f"autotune {time.perf_counter() - t1:.1f} s")
+    log(f"autotune {time.perf_counter() - t1:.1f} s; schedule {M.schedule()}")
     for _ in range(args.warmup):
         M.rk3_step(phys, W, t, cfl=0.5)
     torch.cuda.synchronize()
@@ -204,6 +204,7 @@ def main():
                      "frac": achieved / PEAK_HBM_GBS, "traffic": None,
                      "kernel": "reconstruction (k_recon_weno, both cell types)",
                      "bytes_per_launch": rbytes, "avg_launch_ms": ravg * 1e3},
+        "schedule": M.schedule(),
         "stage": {"algorithmic_bytes": sbytes, "ms": el / args.steps / 3 * 1e3,
                   "achieved_GBs": sbytes / (el / args.steps / 3) / 1e9,
                   "recon_ms": ravg * 1e3, "flux_ms": fms / max(fn, 1)},

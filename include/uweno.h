@@ -162,27 +162,41 @@ uw_status uw_rk3_step(uw_mesh* mesh, const uw_physics* physics, double* W, doubl
 uw_status uw_cfl_dt(uw_mesh* mesh, const uw_physics* physics, const double* W, double cfl,
                     double* dt_dev, void* stream);
 
-/* Many independent meshes advanced together (one launch per RK stage for
- * all of them).  Every mesh must be precomputed with the same scheme; the
- * batch keeps pointers to them (they must outlive it).  W_concat: device
- * FP64, the meshes' states concatenated in order, each [V][n_k].
- * cell_offsets: host [n+1], the start of each mesh's block in W_concat
- * (counted in cells; the block of mesh k holds V * n_k doubles). */
+/* Many independent meshes advanced together.  Every RK stage is one
+ * persistent reconstruction launch per cell type over the 256-cell tiles of
+ * all instances plus one flux launch; the steps of uw_batch_rk3_step are
+ * captured once into a hipGraph and replayed.  Every mesh must be
+ * precomputed with the same scheme and live on one device; the batch copies
+ * their tables (the meshes may be destroyed afterwards).
+ * Batch state: device FP64 [V][N_total], N_total = sum of the instances'
+ * cells; instance k occupies cells [cell_offsets[k], cell_offsets[k+1]) in
+ * its own internal order. */
 uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* physics,
                           uw_batch** out);
+/* cell_offsets: host [n+1]. */
 uw_status uw_batch_offsets(const uw_batch* batch, int64_t* cell_offsets);
-/* n_steps RK3 steps of every instance, each with its own CFL time step
- * (cfl > 0) or dt_fixed (> 0), both clamped to t_end - t_k; t_dev: device
- * [n] times. */
-uw_status uw_batch_rk3_step(uw_batch* batch, double* W_concat, double cfl, double dt_fixed,
+/* n_steps SSP-RK3 steps of every instance, each with its own time step:
+ * cfl * (instance's CFL bound) if dt_fixed <= 0, else dt_fixed, both
+ * clamped to t_end - t_k.  t_dev: device [n] times, advanced on the device.
+ * The first call with a given (W, t_dev, n_steps, cfl, dt_fixed, t_end)
+ * captures a graph; later calls replay it (enqueued on `stream`). */
+uw_status uw_batch_rk3_step(uw_batch* batch, double* W, double cfl, double dt_fixed,
                             double t_end, int32_t n_steps, double* t_dev, void* stream);
 
-/* Chooses launch parameters (threads per block and cells per block of the
- * reconstruction kernel) by timing candidates on the mesh (or batch) and
- * stores them in it; `cache_path` (nullable) is a text file of earlier
- * choices keyed by workload shape, read and updated. */
+/* Chooses the launch schedule (number of persistent blocks of the
+ * reconstruction kernels of each cell type and of the flux kernel: one
+ * block per 256-cell tile, or 1, 2, 4 or 8 blocks per compute unit) by
+ * timing residual evaluations on the mesh or batch (exactly one of them)
+ * and stores it there.  `cache_path` (nullable): a text file of earlier
+ * choices keyed by the workload's shape, read first and appended to. */
 uw_status uw_autotune(uw_mesh* mesh, uw_batch* batch, const uw_physics* physics,
                       const char* cache_path, void* stream);
+
+/* Reads (get, nullable, host [3]) and/or sets (set, nullable) the launch
+ * schedule of a mesh or batch (exactly one): persistent blocks of the
+ * quadrilateral reconstruction, of the triangle reconstruction and of the
+ * flux kernel; 0 = one block per 256-cell tile.  Set is applied before get. */
+uw_status uw_schedule(uw_mesh* mesh, uw_batch* batch, int32_t* get, const int32_t* set);
 
 /* Launch timing (tracing): with enable = 1 every later reconstruction and
  * flux launch of this mesh is bracketed by HIP events on the caller's

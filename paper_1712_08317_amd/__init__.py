@@ -13,7 +13,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libuweno.so")
+# UWENO_LIB may name another build of the library (default: the in-tree one)
+LIB_PATH = os.environ.get("UWENO_LIB", os.path.join(HERE, "libuweno.so"))
 
 UW_OK, UW_EINVAL, UW_EMESH, UW_ESTATE, UW_ENOMEM, UW_EDEVICE, UW_ENONFINITE = range(7)
 UW_BC_PERIODIC, UW_BC_TRANSMISSIVE = 0, 1
@@ -57,7 +58,7 @@ class DiagC(ctypes.Structure):
 EXPORTS = ["uw_last_error", "uw_mesh_upload", "uw_mesh_info", "uw_mesh_export",
            "uw_precompute_geometry", "uw_mesh_table", "uw_residual", "uw_rk3_step", "uw_cfl_dt",
            "uw_batch_create", "uw_batch_offsets", "uw_batch_rk3_step", "uw_autotune", "uw_check",
-           "uw_profile", "uw_mesh_destroy", "uw_batch_destroy"]
+           "uw_profile", "uw_schedule", "uw_mesh_destroy", "uw_batch_destroy"]
 
 
 def _load():
@@ -84,6 +85,7 @@ def _load():
         "uw_autotune": (i32, [vp, vp, ctypes.POINTER(PhysicsC), ctypes.c_char_p, vp]),
         "uw_check": (i32, [vp, vp, vp]),
         "uw_profile": (i32, [vp, i32, vp, vp]),
+        "uw_schedule": (i32, [vp, vp, vp, vp]),
         "uw_mesh_destroy": (None, [vp]),
         "uw_batch_destroy": (None, [vp]),
     }
@@ -216,6 +218,15 @@ class Mesh:
     def check(self, stream=None):
         _check(LIB.uw_check(self.handle, None, _stream(stream)))
 
+    def schedule(self, set_to=None):
+        """The launch schedule (recon quads, recon triangles, flux); 0 = one
+        block per tile.  ``set_to`` (3 ints) replaces it first."""
+        got = np.zeros(3, dtype=np.int32)
+        s = None if set_to is None else np.ascontiguousarray(set_to, dtype=np.int32)
+        _check(LIB.uw_schedule(self.handle, None, got.ctypes.data,
+                               None if s is None else s.ctypes.data))
+        return tuple(int(x) for x in got)
+
     def profile(self, enable=-1):
         """Returns ((recon_ms, flux_ms), (recon_count, flux_count)) recorded
         so far and clears them; enable = 1/0 switches recording on/off."""
@@ -242,6 +253,17 @@ class Batch:
         if h is not None and h.value and LIB is not None:
             LIB.uw_batch_destroy(h)
             self.handle = None
+
+    def to_internal(self, states):
+        """Per-instance states (original order, [V, n_k]) -> batch state [V, N]."""
+        return np.ascontiguousarray(np.concatenate(
+            [m.to_internal(W) for m, W in zip(self.meshes, states)], axis=1))
+
+    def to_original(self, W):
+        """Batch state [V, N] -> list of per-instance states in original order."""
+        W = np.asarray(W)
+        return [m.to_original(W[:, self.offsets[k]:self.offsets[k + 1]])
+                for k, m in enumerate(self.meshes)]
 
     def rk3_step(self, W, t_dev, cfl=0.5, dt_fixed=0.0, t_end=float("inf"), n_steps=1,
                  stream=None):

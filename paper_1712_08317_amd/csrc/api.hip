@@ -1,19 +1,23 @@
 // C-ABI of the uweno library: mesh upload, FP64 precompute, residual,
-// SSP-RK3 steps, CFL time step, batches, error reporting.
+// SSP-RK3 steps (single meshes and batches), CFL time step, launch
+// schedule tuning, launch timing and error reporting.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
+#include <tuple>
+#include <type_traits>
 #include <vector>
 
-#include "../../include/uweno.h"
+#include "uweno.h"
 #include "uw_device.h"
 #include "uw_host.h"
 
-static_assert(uw::kTile == uw::kReconBlock, "tile size and reconstruction block differ");
+static_assert(uw::kTile == uw::kTileCells, "host tile size and device block size differ");
 
 namespace {
 
@@ -28,10 +32,16 @@ uw_status hip_fail(hipError_t e, const char* what) {
   return fail(UW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-#define UW_HIP(call)                                         \
-  do {                                                       \
-    hipError_t e_ = (call);                                  \
-    if (e_ != hipSuccess) return hip_fail(e_, #call);        \
+#define UW_HIP(call)                                  \
+  do {                                                \
+    hipError_t e_ = (call);                           \
+    if (e_ != hipSuccess) return hip_fail(e_, #call); \
+  } while (0)
+
+#define UW_TRY(call)            \
+  do {                          \
+    uw_status s_ = (call);      \
+    if (s_ != UW_OK) return s_; \
   } while (0)
 
 // Device buffer owned by the library.
@@ -78,38 +88,161 @@ std::vector<T> convert(const std::vector<double>& v) {
   }
 }
 
+// Host copy of the device layout of one or more meshes (a batch), FP64.
+struct Staged {
+  int64_t N = 0;
+  int32_t n_inst = 0, n_tq = 0, n_tt = 0, max_len_q = 0, max_len_t = 0;
+  std::vector<uw::Tile> tiles;
+  std::vector<int32_t> tile_off, tile_ids, inst_tiles, fnb;
+  int64_t rows_q = 0, rows_t = 0;
+  std::vector<uint16_t> q_lidx, t_lidx;
+  std::vector<double> q_Y, q_off, q_gam, q_eta, t_Y, t_off, t_gam, t_eta, fgeo;
+};
+
+template <class V, class Get>
+void cat_type(const std::vector<const uw::HostTables*>& ts, bool quad, Get get, int64_t rows_total,
+              const std::vector<int64_t>& row_off, V& out) {
+  size_t K = 0;
+  for (const uw::HostTables* t : ts) {
+    const uw::TypeTables& tt = quad ? t->quad : t->tri;
+    if (tt.Nt > 0) K = get(tt).size() / tt.Nt;
+  }
+  out.assign(K * rows_total, 0);
+  for (size_t k = 0; k < ts.size(); ++k) {
+    const uw::TypeTables& tt = quad ? ts[k]->quad : ts[k]->tri;
+    if (tt.Nt <= 0) continue;
+    const auto& in = get(tt);
+    for (size_t c = 0; c < K; ++c)
+      std::copy(in.begin() + c * tt.Nt, in.begin() + (c + 1) * tt.Nt,
+                out.begin() + c * rows_total + row_off[k]);
+  }
+}
+
+// Concatenates per-mesh tables into the batch layout: cells of instance k
+// occupy [off_k, off_k + n_k); each type's table rows are concatenated by
+// instance; neighbour and staging ids are rebased.
+void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<const uw::HostTables*>& ts,
+              bool linear, Staged& S) {
+  const int n = (int)ms.size();
+  S = Staged();
+  S.n_inst = n;
+  std::vector<int64_t> off(n + 1, 0), qrow(n + 1, 0), trow(n + 1, 0);
+  for (int k = 0; k < n; ++k) {
+    off[k + 1] = off[k] + ms[k]->N;
+    qrow[k + 1] = qrow[k] + ts[k]->quad.Nt;
+    trow[k + 1] = trow[k] + ts[k]->tri.Nt;
+  }
+  S.N = off[n];
+  S.rows_q = qrow[n];
+  S.rows_t = trow[n];
+  // tiles and staging lists: quadrilateral tiles of every instance, then triangles
+  S.inst_tiles.assign(2 * (n + 1), 0);
+  S.tile_off.push_back(0);
+  for (int type = 0; type < 2; ++type) {
+    int32_t count = 0;
+    for (int k = 0; k < n; ++k) {
+      const uw::TypeTables& tt = type == 0 ? ts[k]->quad : ts[k]->tri;
+      const int64_t rows0 = type == 0 ? qrow[k] : trow[k];
+      const int64_t nt = (int64_t)tt.tile_off.size() - 1;
+      for (int64_t j = 0; j < nt; ++j) {
+        uw::Tile tl;
+        tl.first = (int32_t)(off[k] + tt.first + j * uw::kTile);
+        tl.row0 = (int32_t)(rows0 + j * uw::kTile);
+        tl.count = (int32_t)std::min<int64_t>(uw::kTile, tt.Nt - j * uw::kTile);
+        tl.inst = k;
+        S.tiles.push_back(tl);
+        for (int32_t q = tt.tile_off[j]; q < tt.tile_off[j + 1]; ++q)
+          S.tile_ids.push_back((int32_t)(tt.tile_ids[q] + off[k]));
+        S.tile_off.push_back((int32_t)S.tile_ids.size());
+      }
+      count += (int32_t)std::max<int64_t>(nt, 0);
+      S.inst_tiles[type * (n + 1) + k + 1] = count;
+      int32_t& mx = type == 0 ? S.max_len_q : S.max_len_t;
+      mx = std::max(mx, tt.max_tile_len);
+    }
+    (type == 0 ? S.n_tq : S.n_tt) = count;
+  }
+  // per-type tables, structure of arrays with the batch row count
+  for (int type = 0; type < 2; ++type) {
+    const bool q = type == 0;
+    const int64_t R = q ? S.rows_q : S.rows_t;
+    const std::vector<int64_t>& ro = q ? qrow : trow;
+    cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<uint16_t>& { return t.lidx; },
+             R, ro, q ? S.q_lidx : S.t_lidx);
+    cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.Y; }, R,
+             ro, q ? S.q_Y : S.t_Y);
+    cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.off; }, R,
+             ro, q ? S.q_off : S.t_off);
+    cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.gam; }, R,
+             ro, q ? S.q_gam : S.t_gam);
+    if (linear)
+      cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.eta; },
+               R, ro, q ? S.q_eta : S.t_eta);
+  }
+  // face tables
+  S.fnb.assign(4 * S.N, -1);
+  S.fgeo.assign(12 * S.N, 0.0);
+  for (int k = 0; k < n; ++k) {
+    const int64_t Nk = ms[k]->N;
+    for (int c = 0; c < 4; ++c)
+      for (int64_t i = 0; i < Nk; ++i) {
+        const int32_t p = ts[k]->fnb[c * Nk + i];
+        S.fnb[c * S.N + off[k] + i] =
+            p < 0 ? p : (int32_t)((((int64_t)(p >> 3) + off[k]) << 3) | (p & 7));
+      }
+    for (int c = 0; c < 12; ++c)
+      std::copy(ts[k]->fgeo.begin() + c * Nk, ts[k]->fgeo.begin() + (c + 1) * Nk,
+                S.fgeo.begin() + c * S.N + off[k]);
+  }
+}
+
 template <class T>
 struct DevTables {
   bool ready = false;
-  DevBuf q_to, q_ti, q_li, q_Y, q_off, q_gam, q_eta, t_to, t_ti, t_li, t_Y, t_off, t_gam, t_eta,
-      fnb, fgeo;
+  DevBuf tiles, tile_off, tile_ids, inst_tiles, q_li, q_Y, q_off, q_gam, q_eta, t_li, t_Y, t_off,
+      t_gam, t_eta, fnb, fgeo;
   uw::MeshDev<T> view;
   void reset() {
-    for (DevBuf* b : {&q_to, &q_ti, &q_li, &q_Y, &q_off, &q_gam, &q_eta, &t_to, &t_ti, &t_li,
-                      &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fgeo})
+    for (DevBuf* b : {&tiles, &tile_off, &tile_ids, &inst_tiles, &q_li, &q_Y, &q_off, &q_gam,
+                      &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fgeo})
       b->release();
     view = uw::MeshDev<T>();
     ready = false;
   }
 };
 
-}  // namespace
-
-struct uw_mesh {
+// Device state shared by a mesh and a batch: tables in both precisions
+// (uploaded on first use), work buffers, launch schedule and timing.
+struct Engine {
   int device = 0;
-  uw::HostMesh host;
-  uw::HostTables tables;
-  uw::SchemeParams scheme;
-  bool precomputed = false;
+  uw::SchemeDev scheme{1e-3, 3.0, 0};
+  Staged staged;
+  bool staged_ready = false;
   DevTables<double> d64;
   DevTables<float> d32;
   DevBuf FS, Wtmp, dt, partial, flag;
-  int block_recon = 256, block_flux = 256;
-  // optional timing of every launch with HIP events on the caller's stream
+  uw::Schedule sched;
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
-  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;  // kind, (start, stop)
-  ~uw_mesh() {
+  std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+  // captured multi-step graphs, keyed by their arguments
+  std::map<std::tuple<const void*, const void*, int, double, double, double, int>, hipGraphExec_t>
+      graphs;
+  // graphs cannot be captured on the null stream: calls made on it capture
+  // and replay on this blocking stream, which orders itself with the null one
+  hipStream_t own_stream = nullptr;
+  void reset_device() {
+    d64.reset();
+    d32.reset();
+    clear_graphs();
+  }
+  void clear_graphs() {
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    graphs.clear();
+  }
+  ~Engine() {
+    clear_graphs();
+    if (own_stream) (void)hipStreamDestroy(own_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
     for (auto& u : ev_used) {
       (void)hipEventDestroy(u.second.first);
@@ -118,78 +251,84 @@ struct uw_mesh {
   }
 };
 
-struct uw_batch {
-  std::vector<uw_mesh*> meshes;
-  uw_physics physics;
-  std::vector<int64_t> offsets;
-};
-
-namespace {
-
 template <class T>
-DevTables<T>& tables_of(uw_mesh* m);
+DevTables<T>& tables_of(Engine& e);
 template <>
-DevTables<double>& tables_of<double>(uw_mesh* m) {
-  return m->d64;
+DevTables<double>& tables_of<double>(Engine& e) {
+  return e.d64;
 }
 template <>
-DevTables<float>& tables_of<float>(uw_mesh* m) {
-  return m->d32;
+DevTables<float>& tables_of<float>(Engine& e) {
+  return e.d32;
 }
 
 template <class T>
-uw_status ensure_tables(uw_mesh* m) {
-  DevTables<T>& d = tables_of<T>(m);
+uw_status ensure_tables(Engine& E) {
+  DevTables<T>& d = tables_of<T>(E);
   if (d.ready) return UW_OK;
-  UW_HIP(hipSetDevice(m->device));
-  const uw::HostTables& t = m->tables;
-  auto up_type = [&](const uw::TypeTables& tt, DevBuf& to, DevBuf& ti, DevBuf& li, DevBuf& Y,
-                     DevBuf& off, DevBuf& gam, DevBuf& eta, uw::TypeDev<T>& view) -> hipError_t {
-    hipError_t e;
-    if ((e = to.upload(tt.tile_off)) != hipSuccess) return e;
-    if ((e = ti.upload(tt.tile_ids)) != hipSuccess) return e;
-    if ((e = li.upload(tt.lidx)) != hipSuccess) return e;
-    if ((e = Y.upload(convert<T>(tt.Y))) != hipSuccess) return e;
-    if ((e = off.upload(convert<T>(tt.off))) != hipSuccess) return e;
-    if ((e = gam.upload(convert<T>(tt.gam))) != hipSuccess) return e;
-    if ((e = eta.upload(convert<T>(tt.eta))) != hipSuccess) return e;
-    view.Nt = tt.Nt;
-    view.first = tt.first;
-    view.tile_off = to.template as<int32_t>();
-    view.tile_ids = ti.template as<int32_t>();
-    view.lidx = li.template as<uint16_t>();
-    view.max_tile_len = tt.max_tile_len;
-    view.Y = Y.template as<T>();
-    view.off = off.template as<T>();
-    view.gam = gam.template as<T>();
-    view.eta = eta.template as<T>();
-    return hipSuccess;
+  UW_HIP(hipSetDevice(E.device));
+  const Staged& S = E.staged;
+  hipError_t e = hipSuccess;
+  auto up = [&](DevBuf& b, const auto& v) {
+    if (e == hipSuccess) e = b.upload(v);
   };
-  hipError_t e =
-      up_type(t.quad, d.q_to, d.q_ti, d.q_li, d.q_Y, d.q_off, d.q_gam, d.q_eta, d.view.quad);
-  if (e == hipSuccess)
-    e = up_type(t.tri, d.t_to, d.t_ti, d.t_li, d.t_Y, d.t_off, d.t_gam, d.t_eta, d.view.tri);
-  if (e == hipSuccess) e = d.fnb.upload(t.fnb);
-  if (e == hipSuccess) e = d.fgeo.upload(convert<T>(t.fgeo));
+  up(d.tiles, S.tiles);
+  up(d.tile_off, S.tile_off);
+  up(d.tile_ids, S.tile_ids);
+  up(d.inst_tiles, S.inst_tiles);
+  up(d.q_li, S.q_lidx);
+  up(d.q_Y, convert<T>(S.q_Y));
+  up(d.q_off, convert<T>(S.q_off));
+  up(d.q_gam, convert<T>(S.q_gam));
+  up(d.q_eta, convert<T>(S.q_eta));
+  up(d.t_li, S.t_lidx);
+  up(d.t_Y, convert<T>(S.t_Y));
+  up(d.t_off, convert<T>(S.t_off));
+  up(d.t_gam, convert<T>(S.t_gam));
+  up(d.t_eta, convert<T>(S.t_eta));
+  up(d.fnb, S.fnb);
+  up(d.fgeo, convert<T>(S.fgeo));
   if (e == hipErrorOutOfMemory) return fail(UW_ENOMEM, "device tables: out of memory");
   if (e != hipSuccess) return hip_fail(e, "device tables upload");
-  d.view.N = m->host.N;
-  d.view.Nq = m->host.Nq;
-  d.view.fnb = d.fnb.template as<int32_t>();
-  d.view.fgeo = d.fgeo.template as<T>();
+  uw::MeshDev<T>& v = d.view;
+  v.N = S.N;
+  v.n_inst = S.n_inst;
+  v.n_tq = S.n_tq;
+  v.n_tt = S.n_tt;
+  v.tiles = d.tiles.template as<uw::Tile>();
+  v.tile_off = d.tile_off.template as<int32_t>();
+  v.tile_ids = d.tile_ids.template as<int32_t>();
+  v.max_len_q = S.max_len_q;
+  v.max_len_t = S.max_len_t;
+  v.inst_tiles = d.inst_tiles.template as<int32_t>();
+  v.quad.Nt = S.rows_q;
+  v.quad.lidx = d.q_li.template as<uint16_t>();
+  v.quad.Y = d.q_Y.template as<T>();
+  v.quad.off = d.q_off.template as<T>();
+  v.quad.gam = d.q_gam.template as<T>();
+  v.quad.eta = d.q_eta.template as<T>();
+  v.tri.Nt = S.rows_t;
+  v.tri.lidx = d.t_li.template as<uint16_t>();
+  v.tri.Y = d.t_Y.template as<T>();
+  v.tri.off = d.t_off.template as<T>();
+  v.tri.gam = d.t_gam.template as<T>();
+  v.tri.eta = d.t_eta.template as<T>();
+  v.fnb = d.fnb.template as<int32_t>();
+  v.fgeo = d.fgeo.template as<T>();
   d.ready = true;
   return UW_OK;
 }
 
-uw_status ensure_work(uw_mesh* m, int nvar, size_t fs_elem) {
-  const int64_t N = m->host.N;
-  UW_HIP(m->FS.ensure((size_t)N * 8 * nvar * fs_elem));
-  UW_HIP(m->Wtmp.ensure((size_t)N * nvar * sizeof(double)));
-  UW_HIP(m->dt.ensure(sizeof(double)));
-  UW_HIP(m->partial.ensure((size_t)uw::cfl_partials(N) * sizeof(double)));
-  if (!m->flag.p) {
-    UW_HIP(m->flag.ensure(sizeof(int)));
-    UW_HIP(hipMemset(m->flag.p, 0, sizeof(int)));
+uw_status ensure_work(Engine& E, int nvar, size_t fs_elem) {
+  const int64_t N = E.staged.N;
+  const int64_t ntiles = (int64_t)E.staged.n_tq + E.staged.n_tt;
+  UW_HIP(E.FS.ensure((size_t)N * 8 * nvar * fs_elem));
+  UW_HIP(E.Wtmp.ensure((size_t)N * nvar * sizeof(double)));
+  UW_HIP(E.dt.ensure((size_t)E.staged.n_inst * sizeof(double)));
+  UW_HIP(E.partial.ensure((size_t)std::max<int64_t>(ntiles, 1) * sizeof(double)));
+  if (!E.flag.p) {
+    UW_HIP(E.flag.ensure(sizeof(int)));
+    UW_HIP(hipMemset(E.flag.p, 0, sizeof(int)));
   }
   return UW_OK;
 }
@@ -205,19 +344,17 @@ uw_status check_physics(const uw_physics* p) {
   return UW_OK;
 }
 
+int nvar_of(const uw_physics* p) { return p->equation == UW_EULER ? 4 : 1; }
+
 uw::PhysDev phys_dev(const uw_physics* p) {
   return uw::PhysDev{p->equation, p->ax, p->ay, p->gamma};
 }
 
-uw::SchemeDev scheme_dev(const uw_mesh* m) {
-  return uw::SchemeDev{m->scheme.eps, m->scheme.theta, m->scheme.mode};
-}
-
-hipError_t ev_begin(uw_mesh* m, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
+hipError_t ev_begin(Engine& E, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
   for (hipEvent_t* e : {a, b}) {
-    if (!m->ev_pool.empty()) {
-      *e = m->ev_pool.back();
-      m->ev_pool.pop_back();
+    if (!E.ev_pool.empty()) {
+      *e = E.ev_pool.back();
+      E.ev_pool.pop_back();
     } else {
       hipError_t r = hipEventCreate(e);
       if (r != hipSuccess) return r;
@@ -226,53 +363,136 @@ hipError_t ev_begin(uw_mesh* m, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
   return hipEventRecord(*a, st);
 }
 
-// One residual evaluation or RK stage on the given state.
+// One residual evaluation (mode 0) or RK stage (modes 1..3).
 template <class T>
-uw_status stage(uw_mesh* m, const uw_physics* p, int mode, const double* W_in, const double* Wn,
-                double* W_out, double* t, hipStream_t st) {
-  const int nvar = p->equation == UW_EULER ? 4 : 1;
-  DevTables<T>& d = tables_of<T>(m);
-  T* FS = m->FS.template as<T>();
+uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, const double* Wn,
+                double* W_out, hipStream_t st, bool timed) {
+  const int nvar = nvar_of(p);
+  DevTables<T>& d = tables_of<T>(E);
+  T* FS = E.FS.template as<T>();
+  const bool prof = timed && E.profiling;
   hipEvent_t a = nullptr, b = nullptr;
-  if (m->profiling) UW_HIP(ev_begin(m, st, &a, &b));
-  hipError_t e = uw::launch_recon<T>(d.view, scheme_dev(m), nvar, W_in, FS, st);
+  if (prof) UW_HIP(ev_begin(E, st, &a, &b));
+  hipError_t e = uw::launch_recon<T>(d.view, E.scheme, E.sched, nvar, W_in, FS, st);
   if (e != hipSuccess) return hip_fail(e, "reconstruction launch");
-  if (m->profiling) {
+  if (prof) {
     UW_HIP(hipEventRecord(b, st));
-    m->ev_used.push_back({0, {a, b}});
-    UW_HIP(ev_begin(m, st, &a, &b));
+    E.ev_used.push_back({0, {a, b}});
+    UW_HIP(ev_begin(E, st, &a, &b));
   }
-  e = uw::launch_flux<T>(d.view, phys_dev(p), nvar, mode, FS, W_in, Wn, W_out,
-                         m->dt.as<double>(), t, m->flag.as<int>(), m->block_flux, st);
+  e = uw::launch_flux<T>(d.view, phys_dev(p), E.sched, nvar, mode, FS, W_in, Wn, W_out,
+                         E.dt.as<double>(), E.flag.as<int>(), st);
   if (e != hipSuccess) return hip_fail(e, "flux launch");
-  if (m->profiling) {
+  if (prof) {
     UW_HIP(hipEventRecord(b, st));
-    m->ev_used.push_back({1, {a, b}});
+    E.ev_used.push_back({1, {a, b}});
   }
   return UW_OK;
 }
 
 template <class T>
-uw_status prepare(uw_mesh* m, const uw_physics* p) {
-  uw_status s = ensure_tables<T>(m);
-  if (s != UW_OK) return s;
-  return ensure_work(m, p->equation == UW_EULER ? 4 : 1, sizeof(T));
+uw_status prepare(Engine& E, const uw_physics* p) {
+  UW_TRY(ensure_tables<T>(E));
+  return ensure_work(E, nvar_of(p), sizeof(T));
+}
+
+// One SSP-RK3 step of every instance (time step on the device).
+template <class T>
+uw_status rk3(Engine& E, const uw_physics* p, double* W, double cfl, double dt_fixed,
+              double t_end, double* t_dev, hipStream_t st, bool timed) {
+  DevTables<T>& d = tables_of<T>(E);
+  hipError_t e = uw::launch_cfl<T>(d.view, phys_dev(p), nvar_of(p), W, cfl, dt_fixed, t_end,
+                                   t_dev, E.partial.as<double>(), E.dt.as<double>(), st);
+  if (e != hipSuccess) return hip_fail(e, "time-step launch");
+  double* W1 = E.Wtmp.as<double>();
+  UW_TRY(stage<T>(E, p, 1, W, W, W1, st, timed));
+  UW_TRY(stage<T>(E, p, 2, W1, W, W1, st, timed));
+  UW_TRY(stage<T>(E, p, 3, W1, W, W, st, timed));
+  e = uw::launch_advance(E.staged.n_inst, t_dev, E.dt.as<double>(), st);
+  if (e != hipSuccess) return hip_fail(e, "time advance launch");
+  return UW_OK;
 }
 
 template <class T>
-uw_status rk3(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,
-              double t_end, double* t_dev, hipStream_t st) {
-  uw_status s = prepare<T>(m, p);
-  if (s != UW_OK) return s;
-  const int nvar = p->equation == UW_EULER ? 4 : 1;
-  DevTables<T>& d = tables_of<T>(m);
-  hipError_t e = uw::launch_cfl<T>(d.view, phys_dev(p), nvar, W, cfl, dt_fixed, t_end, t_dev,
-                                   m->partial.as<double>(), m->dt.as<double>(), st);
-  if (e != hipSuccess) return hip_fail(e, "time-step launch");
-  double* W1 = m->Wtmp.as<double>();
-  if ((s = stage<T>(m, p, 1, W, W, W1, nullptr, st)) != UW_OK) return s;
-  if ((s = stage<T>(m, p, 2, W1, W, W1, nullptr, st)) != UW_OK) return s;
-  return stage<T>(m, p, 3, W1, W, W, t_dev, st);
+uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, double dt_fixed,
+                    double t_end, int n_steps, double* t_dev, hipStream_t st, bool graph) {
+  UW_TRY(prepare<T>(E, p));
+  if (!graph || n_steps <= 0) {
+    for (int k = 0; k < n_steps; ++k)
+      UW_TRY(rk3<T>(E, p, W, cfl, dt_fixed, t_end, t_dev, st, true));
+    return UW_OK;
+  }
+  if (!st) {
+    if (!E.own_stream) UW_HIP(hipStreamCreate(&E.own_stream));
+    st = E.own_stream;
+  }
+  auto key = std::make_tuple((const void*)W, (const void*)t_dev, n_steps, cfl, dt_fixed, t_end,
+                             p->precision * 16 + p->equation);
+  auto it = E.graphs.find(key);
+  if (it == E.graphs.end()) {
+    UW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    uw_status s = UW_OK;
+    for (int k = 0; k < n_steps && s == UW_OK; ++k)
+      s = rk3<T>(E, p, W, cfl, dt_fixed, t_end, t_dev, st, false);
+    hipGraph_t g = nullptr;
+    hipError_t e = hipStreamEndCapture(st, &g);
+    if (s != UW_OK) {
+      if (g) (void)hipGraphDestroy(g);
+      return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
+    it = E.graphs.emplace(key, ex).first;
+  }
+  UW_HIP(hipGraphLaunch(it->second, st));
+  return UW_OK;
+}
+
+uw_status check_scheme(const uw_scheme* sc) {
+  if (!sc) return fail(UW_EINVAL, "scheme is NULL");
+  if (!(sc->zeta >= 0.0) || !(sc->eps > 0.0) || !(sc->theta >= 1.0))
+    return fail(UW_EINVAL, "scheme needs zeta >= 0, eps > 0, theta >= 1");
+  if (sc->mode != UW_WENO && sc->mode != UW_LINEAR) return fail(UW_EINVAL, "scheme.mode");
+  if (sc->d_scope != UW_D_PER_GP && sc->d_scope != UW_D_PER_CELL)
+    return fail(UW_EINVAL, "scheme.d_scope");
+  return UW_OK;
+}
+
+}  // namespace
+
+struct uw_mesh {
+  uw::HostMesh host;
+  uw::HostTables tables;
+  uw::SchemeParams scheme;
+  bool precomputed = false;
+  Engine eng;
+};
+
+struct uw_batch {
+  std::vector<uw_mesh*> meshes;
+  uw_physics physics;
+  std::vector<int64_t> offsets;
+  Engine eng;
+};
+
+namespace {
+
+uw_status mesh_ready(uw_mesh* m) {
+  if (!m->precomputed) return fail(UW_ESTATE, "call uw_precompute_geometry first");
+  if (m->eng.device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
+  if (!m->eng.staged_ready) {
+    try {
+      assemble({&m->host}, {&m->tables}, m->scheme.mode == 1, m->eng.staged);
+    } catch (const std::bad_alloc&) {
+      return fail(UW_ENOMEM, "host allocation while staging tables");
+    }
+    m->eng.staged_ready = true;
+  }
+  UW_HIP(hipSetDevice(m->eng.device));
+  return UW_OK;
 }
 
 }  // namespace
@@ -292,7 +512,7 @@ uw_status uw_mesh_upload(const uw_mesh_desc* desc, int device, uw_mesh** out) {
   if (desc->n_cells > (int64_t(1) << 28)) return fail(UW_EINVAL, "at most 2^28 cells");
   uw_mesh* m = new (std::nothrow) uw_mesh();
   if (!m) return fail(UW_ENOMEM, "host allocation");
-  m->device = device;
+  m->eng.device = device;
   uw::Error err;
   try {
     if (!uw::build_mesh(desc->n_nodes, desc->node_xy, desc->n_cells, desc->cell_nodes,
@@ -347,20 +567,18 @@ uw_status uw_mesh_export(const uw_mesh* m, int32_t* slots, uint8_t* present, int
 
 uw_status uw_precompute_geometry(uw_mesh* m, const uw_scheme* sc, uw_diag* diag) {
   g_err.clear();
-  if (!m || !sc) return fail(UW_EINVAL, "mesh and scheme must not be NULL");
-  if (!(sc->zeta >= 0.0) || !(sc->eps > 0.0) || !(sc->theta >= 1.0))
-    return fail(UW_EINVAL, "scheme needs zeta >= 0, eps > 0, theta >= 1");
-  if (sc->mode != UW_WENO && sc->mode != UW_LINEAR) return fail(UW_EINVAL, "scheme.mode");
-  if (sc->d_scope != UW_D_PER_GP && sc->d_scope != UW_D_PER_CELL)
-    return fail(UW_EINVAL, "scheme.d_scope");
+  if (!m) return fail(UW_EINVAL, "mesh is NULL");
+  UW_TRY(check_scheme(sc));
   m->scheme.zeta = sc->zeta;
   m->scheme.theta = sc->theta;
   m->scheme.eps = sc->eps;
   m->scheme.optimize = sc->optimize;
   m->scheme.d_scope = sc->d_scope;
   m->scheme.mode = sc->mode;
-  m->d64.reset();
-  m->d32.reset();
+  m->eng.reset_device();
+  m->eng.staged = Staged();
+  m->eng.staged_ready = false;
+  m->eng.scheme = uw::SchemeDev{sc->eps, sc->theta, sc->mode};
   try {
     m->tables = uw::HostTables();
     uw::precompute_tables(m->host, m->scheme, m->tables, uw::default_threads());
@@ -402,79 +620,49 @@ uw_status uw_mesh_table(const uw_mesh* m, int32_t which, double* out) {
 uw_status uw_residual(uw_mesh* m, const uw_physics* p, const double* W, double* L, void* stream) {
   g_err.clear();
   if (!m || !W || !L) return fail(UW_EINVAL, "mesh, W and L must not be NULL");
-  uw_status s = check_physics(p);
-  if (s != UW_OK) return s;
-  if (!m->precomputed) return fail(UW_ESTATE, "uw_residual before uw_precompute_geometry");
-  if (m->device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
+  UW_TRY(check_physics(p));
+  UW_TRY(mesh_ready(m));
   hipStream_t st = (hipStream_t)stream;
-  UW_HIP(hipSetDevice(m->device));
   if (p->precision == UW_FP64) {
-    if ((s = prepare<double>(m, p)) != UW_OK) return s;
-    return stage<double>(m, p, 0, W, W, L, nullptr, st);
+    UW_TRY(prepare<double>(m->eng, p));
+    return stage<double>(m->eng, p, 0, W, W, L, st, true);
   }
-  if ((s = prepare<float>(m, p)) != UW_OK) return s;
-  return stage<float>(m, p, 0, W, W, L, nullptr, st);
+  UW_TRY(prepare<float>(m->eng, p));
+  return stage<float>(m->eng, p, 0, W, W, L, st, true);
 }
 
 uw_status uw_rk3_step(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,
                       double t_end, double* t_dev, void* stream) {
   g_err.clear();
   if (!m || !W || !t_dev) return fail(UW_EINVAL, "mesh, W and t_dev must not be NULL");
-  uw_status s = check_physics(p);
-  if (s != UW_OK) return s;
-  if (!m->precomputed) return fail(UW_ESTATE, "uw_rk3_step before uw_precompute_geometry");
-  if (m->device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
+  UW_TRY(check_physics(p));
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(UW_EINVAL, "need cfl > 0 or dt_fixed > 0");
+  UW_TRY(mesh_ready(m));
   hipStream_t st = (hipStream_t)stream;
-  UW_HIP(hipSetDevice(m->device));
-  if (p->precision == UW_FP64) return rk3<double>(m, p, W, cfl, dt_fixed, t_end, t_dev, st);
-  return rk3<float>(m, p, W, cfl, dt_fixed, t_end, t_dev, st);
+  if (p->precision == UW_FP64)
+    return rk3_steps<double>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, false);
+  return rk3_steps<float>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, false);
 }
 
 uw_status uw_cfl_dt(uw_mesh* m, const uw_physics* p, const double* W, double cfl, double* dt_dev,
                     void* stream) {
   g_err.clear();
   if (!m || !W || !dt_dev) return fail(UW_EINVAL, "mesh, W and dt_dev must not be NULL");
-  uw_status s = check_physics(p);
-  if (s != UW_OK) return s;
-  if (!m->precomputed) return fail(UW_ESTATE, "uw_cfl_dt before uw_precompute_geometry");
-  if (m->device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
+  UW_TRY(check_physics(p));
   if (!(cfl > 0.0)) return fail(UW_EINVAL, "cfl must be > 0");
+  UW_TRY(mesh_ready(m));
   hipStream_t st = (hipStream_t)stream;
-  UW_HIP(hipSetDevice(m->device));
-  const int nvar = p->equation == UW_EULER ? 4 : 1;
   hipError_t e;
   if (p->precision == UW_FP64) {
-    if ((s = prepare<double>(m, p)) != UW_OK) return s;
-    e = uw::launch_cfl<double>(m->d64.view, phys_dev(p), nvar, W, cfl, 0.0, INFINITY, nullptr,
-                               m->partial.as<double>(), dt_dev, st);
+    UW_TRY(prepare<double>(m->eng, p));
+    e = uw::launch_cfl<double>(m->eng.d64.view, phys_dev(p), nvar_of(p), W, cfl, 0.0, INFINITY,
+                               nullptr, m->eng.partial.as<double>(), dt_dev, st);
   } else {
-    if ((s = prepare<float>(m, p)) != UW_OK) return s;
-    e = uw::launch_cfl<float>(m->d32.view, phys_dev(p), nvar, W, cfl, 0.0, INFINITY, nullptr,
-                              m->partial.as<double>(), dt_dev, st);
+    UW_TRY(prepare<float>(m->eng, p));
+    e = uw::launch_cfl<float>(m->eng.d32.view, phys_dev(p), nvar_of(p), W, cfl, 0.0, INFINITY,
+                              nullptr, m->eng.partial.as<double>(), dt_dev, st);
   }
   if (e != hipSuccess) return hip_fail(e, "time-step launch");
-  return UW_OK;
-}
-
-uw_status uw_check(uw_mesh* m, uw_batch* b, void* stream) {
-  g_err.clear();
-  hipStream_t st = (hipStream_t)stream;
-  UW_HIP(hipStreamSynchronize(st));
-  std::vector<uw_mesh*> ms;
-  if (m) ms.push_back(m);
-  if (b) ms.insert(ms.end(), b->meshes.begin(), b->meshes.end());
-  bool bad = false;
-  for (uw_mesh* x : ms) {
-    if (!x->flag.p) continue;
-    int h = 0;
-    UW_HIP(hipMemcpy(&h, x->flag.p, sizeof(int), hipMemcpyDeviceToHost));
-    if (h) {
-      bad = true;
-      UW_HIP(hipMemset(x->flag.p, 0, sizeof(int)));
-    }
-  }
-  if (bad) return fail(UW_ENONFINITE, "non-finite value or non-positive density in a step");
   return UW_OK;
 }
 
@@ -482,25 +670,40 @@ uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* p
   g_err.clear();
   if (!meshes || !out || n < 1) return fail(UW_EINVAL, "need meshes, out and n >= 1");
   *out = nullptr;
-  uw_status s = check_physics(p);
-  if (s != UW_OK) return s;
+  UW_TRY(check_physics(p));
+  std::vector<const uw::HostMesh*> hm;
+  std::vector<const uw::HostTables*> ht;
+  int64_t total = 0;
+  for (int32_t k = 0; k < n; ++k) {
+    uw_mesh* m = meshes[k];
+    if (!m || !m->precomputed) return fail(UW_ESTATE, "every batch mesh must be precomputed");
+    if (m->eng.device < 0 || m->eng.device != meshes[0]->eng.device)
+      return fail(UW_EINVAL, "batch meshes must live on one device");
+    if (m->scheme.mode != meshes[0]->scheme.mode || m->scheme.eps != meshes[0]->scheme.eps ||
+        m->scheme.theta != meshes[0]->scheme.theta)
+      return fail(UW_EINVAL, "batch meshes must share one scheme");
+    hm.push_back(&m->host);
+    ht.push_back(&m->tables);
+    total += m->host.N;
+  }
+  if (total > (int64_t(1) << 28)) return fail(UW_EINVAL, "at most 2^28 cells in a batch");
   uw_batch* b = new (std::nothrow) uw_batch();
   if (!b) return fail(UW_ENOMEM, "host allocation");
   b->physics = *p;
   b->offsets.push_back(0);
   for (int32_t k = 0; k < n; ++k) {
-    uw_mesh* m = meshes[k];
-    if (!m || !m->precomputed) {
-      delete b;
-      return fail(UW_ESTATE, "every batch mesh must be precomputed");
-    }
-    if (m->device != meshes[0]->device) {
-      delete b;
-      return fail(UW_EINVAL, "batch meshes must live on one device");
-    }
-    b->meshes.push_back(m);
-    b->offsets.push_back(b->offsets.back() + m->host.N);
+    b->meshes.push_back(meshes[k]);
+    b->offsets.push_back(b->offsets.back() + meshes[k]->host.N);
   }
+  b->eng.device = meshes[0]->eng.device;
+  b->eng.scheme = meshes[0]->eng.scheme;
+  try {
+    assemble(hm, ht, meshes[0]->scheme.mode == 1, b->eng.staged);
+  } catch (const std::bad_alloc&) {
+    delete b;
+    return fail(UW_ENOMEM, "host allocation while staging the batch");
+  }
+  b->eng.staged_ready = true;
   *out = b;
   return UW_OK;
 }
@@ -517,123 +720,167 @@ uw_status uw_batch_rk3_step(uw_batch* b, double* W, double cfl, double dt_fixed,
   g_err.clear();
   if (!b || !W || !t_dev || n_steps < 0) return fail(UW_EINVAL, "batch, W, t_dev, n_steps >= 0");
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(UW_EINVAL, "need cfl > 0 or dt_fixed > 0");
-  const int nvar = b->physics.equation == UW_EULER ? 4 : 1;
-  for (int32_t step = 0; step < n_steps; ++step)
-    for (size_t k = 0; k < b->meshes.size(); ++k) {
-      uw_status s = uw_rk3_step(b->meshes[k], &b->physics, W + nvar * b->offsets[k], cfl, dt_fixed,
-                                t_end, t_dev + k, stream);
-      if (s != UW_OK) return s;
-    }
-  return UW_OK;
+  UW_HIP(hipSetDevice(b->eng.device));
+  hipStream_t st = (hipStream_t)stream;
+  if (b->physics.precision == UW_FP64)
+    return rk3_steps<double>(b->eng, &b->physics, W, cfl, dt_fixed, t_end, n_steps, t_dev, st,
+                             true);
+  return rk3_steps<float>(b->eng, &b->physics, W, cfl, dt_fixed, t_end, n_steps, t_dev, st,
+                          true);
 }
 
 uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* cache_path,
                       void* stream) {
   g_err.clear();
-  if (!m && !b) return fail(UW_EINVAL, "need a mesh or a batch");
-  uw_status s = check_physics(p);
-  if (s != UW_OK) return s;
-  std::vector<uw_mesh*> ms;
-  if (m) ms.push_back(m);
-  if (b) ms.insert(ms.end(), b->meshes.begin(), b->meshes.end());
+  if ((!m) == (!b)) return fail(UW_EINVAL, "give exactly one of a mesh or a batch");
+  UW_TRY(check_physics(p));
+  if (m) UW_TRY(mesh_ready(m));
+  Engine& E = m ? m->eng : b->eng;
+  UW_HIP(hipSetDevice(E.device));
   hipStream_t st = (hipStream_t)stream;
-  const int nvar = p->equation == UW_EULER ? 4 : 1;
-  for (uw_mesh* x : ms) {
-    if (!x->precomputed) return fail(UW_ESTATE, "autotune before precompute");
-    if (x->device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
-    char key[160];
-    std::snprintf(key, sizeof(key), "%lld %lld %d %d %d", (long long)x->host.N,
-                  (long long)x->host.Nq, nvar, p->precision, x->scheme.mode);
-    bool found = false;
-    if (cache_path) {
-      if (FILE* f = std::fopen(cache_path, "r")) {
-        char line[256];
-        while (std::fgets(line, sizeof(line), f)) {
-          long long a, bq;
-          int c, d, e, br, bf;
-          if (std::sscanf(line, "%lld %lld %d %d %d %d %d", &a, &bq, &c, &d, &e, &br, &bf) == 7) {
-            char k2[160];
-            std::snprintf(k2, sizeof(k2), "%lld %lld %d %d %d", a, bq, c, d, e);
-            if (std::strcmp(k2, key) == 0 && br > 0 && br <= 256 && bf > 0 && bf <= 256) {
-              x->block_recon = br;
-              x->block_flux = bf;
-              found = true;
-            }
+  const int nvar = nvar_of(p);
+  char key[200];
+  std::snprintf(key, sizeof(key), "%lld %d %d %d %d %d %d", (long long)E.staged.N,
+                E.staged.n_inst, E.staged.n_tq, E.staged.n_tt, nvar, p->precision,
+                E.scheme.mode);
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "r")) {
+      char line[320];
+      bool found = false;
+      while (std::fgets(line, sizeof(line), f)) {
+        long long a;
+        int c1, c2, c3, c4, c5, c6, rq, rt, fl;
+        if (std::sscanf(line, "%lld %d %d %d %d %d %d %d %d %d", &a, &c1, &c2, &c3, &c4, &c5, &c6,
+                        &rq, &rt, &fl) == 10) {
+          char k2[200];
+          std::snprintf(k2, sizeof(k2), "%lld %d %d %d %d %d %d", a, c1, c2, c3, c4, c5, c6);
+          if (std::strcmp(k2, key) == 0 && rq >= 0 && rt >= 0 && fl >= 0) {
+            E.sched = uw::Schedule{rq, rt, fl};
+            found = true;
           }
         }
-        std::fclose(f);
       }
-    }
-    if (found) continue;
-    UW_HIP(hipSetDevice(x->device));
-    s = p->precision == UW_FP64 ? prepare<double>(x, p) : prepare<float>(x, p);
-    if (s != UW_OK) return s;
-    // a uniform admissible state to time the kernels on
-    std::vector<double> h((size_t)nvar * x->host.N);
-    for (int64_t i = 0; i < x->host.N; ++i) {
-      if (nvar == 4) {
-        h[i] = 1.0;
-        h[x->host.N + i] = 0.5;
-        h[2 * x->host.N + i] = 0.25;
-        h[3 * x->host.N + i] = 2.5;
-      } else {
-        h[i] = 1.0;
-      }
-    }
-    DevBuf Wt, Lt;
-    UW_HIP(Wt.upload(h));
-    UW_HIP(Lt.ensure(h.size() * sizeof(double)));
-    hipEvent_t e0, e1;
-    UW_HIP(hipEventCreate(&e0));
-    UW_HIP(hipEventCreate(&e1));
-    const int cands[3] = {64, 128, 256};
-    for (int which = 1; which < 2; ++which) {
-      int* knob = &x->block_flux;
-      int best_c = *knob;
-      float best = 1e30f;
-      for (int c : cands) {
-        *knob = c;
-        float tot = 0.0f;
-        for (int rep = 0; rep < 4; ++rep) {
-          UW_HIP(hipEventRecord(e0, st));
-          s = p->precision == UW_FP64
-                  ? stage<double>(x, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(), nullptr, st)
-                  : stage<float>(x, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(), nullptr, st);
-          if (s != UW_OK) return s;
-          UW_HIP(hipEventRecord(e1, st));
-          UW_HIP(hipEventSynchronize(e1));
-          float ms = 0.0f;
-          UW_HIP(hipEventElapsedTime(&ms, e0, e1));
-          if (rep > 0) tot += ms;
-        }
-        if (tot < best) {
-          best = tot;
-          best_c = c;
-        }
-      }
-      *knob = best_c;
-    }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    if (cache_path) {
-      if (FILE* f = std::fopen(cache_path, "a")) {
-        std::fprintf(f, "%s %d %d\n", key, x->block_recon, x->block_flux);
-        std::fclose(f);
+      std::fclose(f);
+      if (found) {
+        E.clear_graphs();
+        return UW_OK;
       }
     }
   }
+  UW_TRY(p->precision == UW_FP64 ? prepare<double>(E, p) : prepare<float>(E, p));
+  // a uniform admissible state to time the kernels on
+  const int64_t N = E.staged.N;
+  std::vector<double> h((size_t)nvar * N);
+  for (int64_t i = 0; i < N; ++i) {
+    if (nvar == 4) {
+      h[i] = 1.0;
+      h[N + i] = 0.5;
+      h[2 * N + i] = 0.25;
+      h[3 * N + i] = 2.5;
+    } else {
+      h[i] = 1.0;
+    }
+  }
+  DevBuf Wt, Lt;
+  UW_HIP(Wt.upload(h));
+  UW_HIP(Lt.ensure(h.size() * sizeof(double)));
+  int cus = 256;
+  UW_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, E.device));
+  hipEvent_t e0, e1;
+  UW_HIP(hipEventCreate(&e0));
+  UW_HIP(hipEventCreate(&e1));
+  // candidate launch shapes: one block per tile (0) or k persistent blocks per CU
+  const int mult[5] = {0, 1, 2, 4, 8};
+  uw_status s = UW_OK;
+  for (int knob = 0; knob < 3 && s == UW_OK; ++knob) {
+    int* val = knob == 0 ? &E.sched.recon_q : knob == 1 ? &E.sched.recon_t : &E.sched.flux;
+    int best_v = *val;
+    float best = 1e30f;
+    for (int c : mult) {
+      *val = c * cus;
+      float tot = 0.0f;
+      for (int rep = 0; rep < 4 && s == UW_OK; ++rep) {
+        hipError_t e = hipEventRecord(e0, st);
+        if (e == hipSuccess) {
+          s = p->precision == UW_FP64
+                  ? stage<double>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(), st,
+                                  false)
+                  : stage<float>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(), st,
+                                 false);
+          if (s == UW_OK) e = hipEventRecord(e1, st);
+          if (s == UW_OK && e == hipSuccess) e = hipEventSynchronize(e1);
+          float ms = 0.0f;
+          if (s == UW_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+          if (rep > 0) tot += ms;
+        }
+        if (e != hipSuccess && s == UW_OK) s = hip_fail(e, "autotune timing");
+      }
+      if (s == UW_OK && tot < best) {
+        best = tot;
+        best_v = *val;
+      }
+    }
+    *val = best_v;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (s != UW_OK) return s;
+  E.clear_graphs();
+  if (cache_path) {
+    if (FILE* f = std::fopen(cache_path, "a")) {
+      std::fprintf(f, "%s %d %d %d\n", key, E.sched.recon_q, E.sched.recon_t, E.sched.flux);
+      std::fclose(f);
+    }
+  }
+  return UW_OK;
+}
+
+uw_status uw_schedule(uw_mesh* m, uw_batch* b, int32_t* get, const int32_t* set) {
+  g_err.clear();
+  if ((!m) == (!b)) return fail(UW_EINVAL, "give exactly one of a mesh or a batch");
+  Engine& E = m ? m->eng : b->eng;
+  if (set) {
+    for (int k = 0; k < 3; ++k)
+      if (set[k] < 0) return fail(UW_EINVAL, "schedule entries must be >= 0");
+    E.sched = uw::Schedule{set[0], set[1], set[2]};
+    E.clear_graphs();
+  }
+  if (get) {
+    get[0] = E.sched.recon_q;
+    get[1] = E.sched.recon_t;
+    get[2] = E.sched.flux;
+  }
+  return UW_OK;
+}
+
+uw_status uw_check(uw_mesh* m, uw_batch* b, void* stream) {
+  g_err.clear();
+  hipStream_t st = (hipStream_t)stream;
+  UW_HIP(hipStreamSynchronize(st));
+  bool bad = false;
+  for (Engine* E : {m ? &m->eng : nullptr, b ? &b->eng : nullptr}) {
+    if (!E || !E->flag.p) continue;
+    int h = 0;
+    UW_HIP(hipMemcpy(&h, E->flag.p, sizeof(int), hipMemcpyDeviceToHost));
+    if (h) {
+      bad = true;
+      UW_HIP(hipMemset(E->flag.p, 0, sizeof(int)));
+    }
+  }
+  if (bad) return fail(UW_ENONFINITE, "non-finite value or non-positive density in a step");
   return UW_OK;
 }
 
 uw_status uw_profile(uw_mesh* m, int32_t enable, double* ms, int64_t* count) {
   g_err.clear();
   if (!m) return fail(UW_EINVAL, "mesh is NULL");
+  Engine& E = m->eng;
   if (ms || count) {
     for (int k = 0; k < 2; ++k) {
       if (ms) ms[k] = 0.0;
       if (count) count[k] = 0;
     }
-    for (auto& u : m->ev_used) {
+    for (auto& u : E.ev_used) {
       UW_HIP(hipEventSynchronize(u.second.second));
       float t = 0.0f;
       UW_HIP(hipEventElapsedTime(&t, u.second.first, u.second.second));
@@ -641,12 +888,12 @@ uw_status uw_profile(uw_mesh* m, int32_t enable, double* ms, int64_t* count) {
       if (count) count[u.first] += 1;
     }
   }
-  for (auto& u : m->ev_used) {
-    m->ev_pool.push_back(u.second.first);
-    m->ev_pool.push_back(u.second.second);
+  for (auto& u : E.ev_used) {
+    E.ev_pool.push_back(u.second.first);
+    E.ev_pool.push_back(u.second.second);
   }
-  m->ev_used.clear();
-  if (enable >= 0) m->profiling = enable != 0;
+  E.ev_used.clear();
+  if (enable >= 0) E.profiling = enable != 0;
   return UW_OK;
 }
 

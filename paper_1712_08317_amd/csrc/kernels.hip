@@ -101,12 +101,12 @@ __device__ inline void load_state<double, 4>(const double* p, double* x) {
   x[3] = b.y;
 }
 
-// Stages the cell averages read by one tile's stencils into LDS (FP64) and
-// returns the list length; every thread of the block must call it.
+// Stages the cell averages read by one tile's stencils into LDS (FP64),
+// then synchronises the block.  Returns the staged list length.
 template <int V>
 __device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const int32_t* tile_off,
-                                 const int32_t* __restrict__ tile_ids, double* lds) {
-  const int beg = tile_off[blockIdx.x], len = tile_off[blockIdx.x + 1] - beg;
+                                 const int32_t* __restrict__ tile_ids, int tile, double* lds) {
+  const int beg = tile_off[tile], len = tile_off[tile + 1] - beg;
   for (int k = threadIdx.x; k < len; k += blockDim.x) {
     const int64_t id = tile_ids[beg + k];
 #pragma unroll
@@ -116,17 +116,13 @@ __device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const 
   return len;
 }
 
+// WENO point values of one cell at its 2n Gauss points (paper Sec. 3.4).
 template <typename T, int NF, int V>
-__global__ __launch_bounds__(kReconBlock, sizeof(T) == 4 ? 2 : 1) void k_recon_weno(const double* __restrict__ W,
-                                                            int64_t N, TypeDev<T> td,
-                                                            T* __restrict__ FS, T eps, T theta) {
+__device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, int64_t i, const double* lds,
+                                 int len, T* __restrict__ FS, T eps, T theta) {
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, G = 2 * NF;
-  extern __shared__ double lds[];
-  const int len = stage_tile<V>(W, N, td.tile_off, td.tile_ids, lds);
-  const int64_t r = (int64_t)blockIdx.x * kReconBlock + threadIdx.x;
-  if (r >= td.Nt) return;
-  const int64_t n = td.Nt, i = td.first + r;
+  const int64_t n = td.Nt;
   double w0[V];
   const int l0 = td.lidx[r];
 #pragma unroll
@@ -140,7 +136,7 @@ __global__ __launch_bounds__(kReconBlock, sizeof(T) == 4 ? 2 : 1) void k_recon_w
     for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
   // candidate gradients g_j = Y_j (dW_a, dW_b) and indicators beta_j = |g_j|^2
-  T gx[M][V], gy[M][V], be[M][V];
+  T gx[M][V], gy[M][V], be[M][V], bpe[M][V];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
     const T y00 = td.Y[(j * 4 + 0) * n + r], y01 = td.Y[(j * 4 + 1) * n + r];
@@ -151,6 +147,7 @@ __global__ __launch_bounds__(kReconBlock, sizeof(T) == 4 ? 2 : 1) void k_recon_w
       gx[j][v] = y00 * dW[a][v] + y01 * dW[b][v];
       gy[j][v] = y10 * dW[a][v] + y11 * dW[b][v];
       be[j][v] = gx[j][v] * gx[j][v] + gy[j][v] * gy[j][v];
+      bpe[j][v] = be[j][v] + eps;
     }
   }
 #pragma unroll 1
@@ -185,15 +182,14 @@ __global__ __launch_bounds__(kReconBlock, sizeof(T) == 4 ? 2 : 1) void k_recon_w
       for (int j = 0; j < M; ++j) {
         const T d = fma(ox, gx[j][v], oy * gy[j][v]);
         const T b = be[j][v];
-        const T be_eps = b + eps;
-        // q = beta (1 + t + t^2) + eps with t = gamma beta: q = beta u + (beta + eps), u = t + t^2
+        // q = beta u + (beta + eps) with u = t + t^2, t = gamma beta
         T t = gp[j] * b;
-        T q = fma(b, fma(t, t, t), be_eps);
+        T q = fma(b, fma(t, t, t), bpe[j][v]);
         T al = gp[j] * rcp(q * q);
         Dp += al;
         Np = fma(al, d, Np);
         t = gm[j] * b;
-        q = fma(b, fma(t, t, t), be_eps);
+        q = fma(b, fma(t, t, t), bpe[j][v]);
         al = gm[j] * rcp(q * q);
         Dm += al;
         Nm = fma(al, d, Nm);
@@ -204,17 +200,13 @@ __global__ __launch_bounds__(kReconBlock, sizeof(T) == 4 ? 2 : 1) void k_recon_w
   }
 }
 
+// Point values of the quadratic P^2 (eq. (polynomial-eta)): the linear scheme.
 template <typename T, int NF, int V>
-__global__ __launch_bounds__(kReconBlock) void k_recon_linear(const double* __restrict__ W,
-                                                              int64_t N, TypeDev<T> td,
-                                                              T* __restrict__ FS) {
+__device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, int64_t i, const double* lds,
+                                   int len, T* __restrict__ FS) {
   using L = Layout<NF>;
   constexpr int S = L::S, G = 2 * NF;
-  extern __shared__ double lds[];
-  const int len = stage_tile<V>(W, N, td.tile_off, td.tile_ids, lds);
-  const int64_t r = (int64_t)blockIdx.x * kReconBlock + threadIdx.x;
-  if (r >= td.Nt) return;
-  const int64_t n = td.Nt, i = td.first + r;
+  const int64_t n = td.Nt;
   double w0[V];
   const int l0 = td.lidx[r];
 #pragma unroll
@@ -241,6 +233,31 @@ __global__ __launch_bounds__(kReconBlock) void k_recon_linear(const double* __re
 #pragma unroll
     for (int v = 0; v < V; ++v) R[v] = (T)w0[v] + acc[v];
     store_state<T, V>(FS + (i * 8 + g) * V, R);
+  }
+}
+
+// Persistent reconstruction over the tiles of one cell type: each block
+// takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+template <typename T, int NF, int V, bool LINEAR>
+// Occupancy measured on gfx950: the quadrilateral kernel runs fastest with
+// the whole register file (1 wave per SIMD), the triangle kernel with 2.
+__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 ? 2 : 1) void k_recon(
+    const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta) {
+  extern __shared__ double lds[];
+  const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
+  const int t0 = NF == 4 ? 0 : m.n_tq, nt = NF == 4 ? m.n_tq : m.n_tt;
+  for (int k = blockIdx.x; k < nt; k += gridDim.x) {
+    const int tile = t0 + k;
+    const Tile tl = m.tiles[tile];
+    const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);
+    if ((int)threadIdx.x < tl.count) {
+      const int64_t r = tl.row0 + threadIdx.x, i = tl.first + threadIdx.x;
+      if (LINEAR)
+        linear_cell<T, NF, V>(td, r, i, lds, len, FS);
+      else
+        weno_cell<T, NF, V>(td, r, i, lds, len, FS, eps, theta);
+    }
+    __syncthreads();   // the next tile overwrites the staged values
   }
 }
 
@@ -303,74 +320,77 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
 }
 
 template <typename T, int V, int MODE>
-__global__ __launch_bounds__(256) void k_flux(MeshDev<T> m, PhysDev p, const T* __restrict__ FS,
-                                              const double* W_in, const double* Wn,
-                                              double* W_out,
-                                              const double* __restrict__ dtp, double* tp,
-                                              int* flag) {
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
+                                                     const T* __restrict__ FS, const double* W_in,
+                                                     const double* Wn, double* W_out,
+                                                     const double* __restrict__ dtp, int* flag) {
   const int64_t N = m.N;
-  if (i >= N) return;
-  const int nf = i < m.Nq ? 4 : 3;
-  T acc[V];
+  const int ntiles = m.n_tq + m.n_tt;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const Tile tl = m.tiles[tile];
+    if ((int)threadIdx.x >= tl.count) continue;
+    const int64_t i = tl.first + threadIdx.x;
+    const int nf = tile < m.n_tq ? 4 : 3;
+    T acc[V];
 #pragma unroll
-  for (int v = 0; v < V; ++v) acc[v] = 0;
-  bool bad = false;
-  for (int k = 0; k < nf; ++k) {
-    const int32_t pk = m.fnb[k * N + i];
-    const T nx = m.fgeo[(k * 3 + 0) * N + i];
-    const T ny = m.fgeo[(k * 3 + 1) * N + i];
-    const T coef = m.fgeo[(k * 3 + 2) * N + i];
-    T o0[V], o1[V], t0[V], t1[V];
-    load_state<T, V>(FS + (i * 8 + 2 * k) * V, o0);
-    load_state<T, V>(FS + (i * 8 + 2 * k + 1) * V, o1);
-    bool left = true;
-    if (pk < 0) {
+    for (int v = 0; v < V; ++v) acc[v] = 0;
+    bool bad = false;
+    for (int k = 0; k < nf; ++k) {
+      const int32_t pk = m.fnb[k * N + i];
+      const T nx = m.fgeo[(k * 3 + 0) * N + i];
+      const T ny = m.fgeo[(k * 3 + 1) * N + i];
+      const T coef = m.fgeo[(k * 3 + 2) * N + i];
+      T o0[V], o1[V], t0[V], t1[V];
+      load_state<T, V>(FS + (i * 8 + 2 * k) * V, o0);
+      load_state<T, V>(FS + (i * 8 + 2 * k + 1) * V, o1);
+      bool left = true;
+      if (pk < 0) {
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        t0[v] = o0[v];
-        t1[v] = o1[v];
+        for (int v = 0; v < V; ++v) {
+          t0[v] = o0[v];
+          t1[v] = o1[v];
+        }
+      } else {
+        const int64_t c = pk >> 3;
+        const int kp = (pk >> 1) & 3;
+        left = (pk & 1) != 0;
+        // the neighbour's Gauss points run the other way along the face
+        load_state<T, V>(FS + (c * 8 + 2 * kp + 1) * V, t0);
+        load_state<T, V>(FS + (c * 8 + 2 * kp) * V, t1);
       }
-    } else {
-      const int64_t c = pk >> 3;
-      const int kp = (pk >> 1) & 3;
-      left = (pk & 1) != 0;
-      load_state<T, V>(FS + (c * 8 + 2 * kp + 1) * V, t0);
-      load_state<T, V>(FS + (c * 8 + 2 * kp) * V, t1);
-    }
-    if constexpr (V == 4) bad |= !(o0[0] > T(0)) || !(o1[0] > T(0));
-    T F0[V], F1[V];
-    if (left) {
-      face_flux<T, V>(o0, t0, nx, ny, p, F0);
-      face_flux<T, V>(o1, t1, nx, ny, p, F1);
-    } else {
-      face_flux<T, V>(t0, o0, nx, ny, p, F0);
-      face_flux<T, V>(t1, o1, nx, ny, p, F1);
-    }
-    const T sc = left ? coef : -coef;
+      if constexpr (V == 4) bad |= !(o0[0] > T(0)) || !(o1[0] > T(0));
+      T F0[V], F1[V];
+      if (left) {
+        face_flux<T, V>(o0, t0, nx, ny, p, F0);
+        face_flux<T, V>(o1, t1, nx, ny, p, F1);
+      } else {
+        face_flux<T, V>(t0, o0, nx, ny, p, F0);
+        face_flux<T, V>(t1, o1, nx, ny, p, F1);
+      }
+      const T sc = left ? coef : -coef;
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] += sc * (F0[v] + F1[v]);
-  }
-  double dt = 0.0;
-  if (MODE != 0) dt = *dtp;
-#pragma unroll
-  for (int v = 0; v < V; ++v) {
-    const double Lv = -(double)acc[v];
-    double out;
-    if (MODE == 0) {
-      out = Lv;
-    } else if (MODE == 1) {
-      out = W_in[v * N + i] + dt * Lv;
-    } else if (MODE == 2) {
-      out = 0.75 * Wn[v * N + i] + 0.25 * (W_in[v * N + i] + dt * Lv);
-    } else {
-      out = Wn[v * N + i] / 3.0 + 2.0 / 3.0 * (W_in[v * N + i] + dt * Lv);
+      for (int v = 0; v < V; ++v) acc[v] += sc * (F0[v] + F1[v]);
     }
-    bad |= !isfinite(out);
-    W_out[v * N + i] = out;
+    double dt = 0.0;
+    if (MODE != 0) dt = dtp[tl.inst];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      const double Lv = -(double)acc[v];
+      double out;
+      if (MODE == 0) {
+        out = Lv;
+      } else if (MODE == 1) {
+        out = W_in[v * N + i] + dt * Lv;
+      } else if (MODE == 2) {
+        out = 0.75 * Wn[v * N + i] + 0.25 * (W_in[v * N + i] + dt * Lv);
+      } else {
+        out = Wn[v * N + i] / 3.0 + 2.0 / 3.0 * (W_in[v * N + i] + dt * Lv);
+      }
+      bad |= !isfinite(out);
+      W_out[v * N + i] = out;
+    }
+    if (bad && flag) *flag = 1;
   }
-  if (bad && flag) *flag = 1;
-  if (MODE == 3 && i == 0 && tp) *tp = *tp + dt;
 }
 
 __device__ inline double wave_min(double x) {
@@ -379,15 +399,19 @@ __device__ inline double wave_min(double x) {
   return x;
 }
 
+// Local time-step bound of every cell of one tile, reduced to the tile's
+// minimum (wavefront then block).
 template <typename T, int V>
-__global__ __launch_bounds__(kCflBlock) void k_cfl(MeshDev<T> m, PhysDev p,
-                                                   const double* __restrict__ W,
-                                                   double* __restrict__ partial) {
-  __shared__ double red[kCflBlock / 64];
-  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(kTileCells) void k_cfl(MeshDev<T> m, PhysDev p,
+                                                    const double* __restrict__ W,
+                                                    double* __restrict__ partial) {
+  __shared__ double red[kTileCells / 64];
+  const int tile = blockIdx.x;
+  const Tile tl = m.tiles[tile];
   const int64_t N = m.N;
   double x = INFINITY;
-  if (i < N) {
+  if ((int)threadIdx.x < tl.count) {
+    const int64_t i = tl.first + threadIdx.x;
     double u, v, c;
     if (V == 4) {
       const double rho = W[i], mu = W[N + i], mv = W[2 * N + i], E = W[3 * N + i];
@@ -400,7 +424,7 @@ __global__ __launch_bounds__(kCflBlock) void k_cfl(MeshDev<T> m, PhysDev p,
       v = p.ay;
       c = 0.0;
     }
-    const int nf = i < m.Nq ? 4 : 3;
+    const int nf = tile < m.n_tq ? 4 : 3;
     double s = 0.0;
     for (int k = 0; k < nf; ++k) {
       const double nx = m.fgeo[(k * 3 + 0) * N + i], ny = m.fgeo[(k * 3 + 1) * N + i];
@@ -415,123 +439,129 @@ __global__ __launch_bounds__(kCflBlock) void k_cfl(MeshDev<T> m, PhysDev p,
   __syncthreads();
   if (threadIdx.x == 0) {
     double b = red[0];
-    for (int w = 1; w < kCflBlock / 64; ++w) b = fmin(b, red[w]);
-    partial[blockIdx.x] = b;
+    for (int w = 1; w < kTileCells / 64; ++w) b = fmin(b, red[w]);
+    partial[tile] = b;
   }
 }
 
-__global__ __launch_bounds__(1024) void k_cfl_final(const double* __restrict__ partial,
-                                                    int64_t np, double cfl, double dt_fixed,
-                                                    double t_end, const double* t, double* dt) {
-  __shared__ double red[16];
+// One wavefront per instance: the minimum over the instance's tiles.
+template <typename T>
+__global__ __launch_bounds__(64) void k_cfl_final(MeshDev<T> m, const double* __restrict__ partial,
+                                                  double cfl, double dt_fixed, double t_end,
+                                                  const double* t, double* dt) {
+  const int k = blockIdx.x;
   double x = INFINITY;
-  if (dt_fixed <= 0.0)
-    for (int64_t k = threadIdx.x; k < np; k += blockDim.x) x = fmin(x, partial[k]);
+  if (dt_fixed <= 0.0) {
+    const int q0 = m.inst_tiles[k], q1 = m.inst_tiles[k + 1];
+    const int s0 = m.n_tq + m.inst_tiles[m.n_inst + 1 + k];
+    const int s1 = m.n_tq + m.inst_tiles[m.n_inst + 1 + k + 1];
+    for (int j = q0 + threadIdx.x; j < q1; j += 64) x = fmin(x, partial[j]);
+    for (int j = s0 + threadIdx.x; j < s1; j += 64) x = fmin(x, partial[j]);
+  }
   x = wave_min(x);
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-  if (lane == 0) red[wid] = x;
-  __syncthreads();
   if (threadIdx.x == 0) {
-    double b = red[0];
-    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) b = fmin(b, red[w]);
-    double d = dt_fixed > 0.0 ? dt_fixed : cfl * b;
-    const double rest = t_end - (t ? *t : 0.0);
+    double d = dt_fixed > 0.0 ? dt_fixed : cfl * x;
+    const double rest = t_end - (t ? t[k] : 0.0);
     d = fmin(d, rest);
-    *dt = d > 0.0 ? d : 0.0;
+    dt[k] = d > 0.0 ? d : 0.0;
   }
 }
 
-template <typename F>
-hipError_t grid_launch(int64_t n, int block, F&& f) {
-  if (n <= 0) return hipSuccess;
-  const int64_t grid = (n + block - 1) / block;
-  f((unsigned)grid);
-  return hipGetLastError();
+__global__ void k_advance(int n, double* t, const double* dt) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n) t[k] += dt[k];
 }
 
 }  // namespace
 
 template <typename T>
-hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, int nvar, const double* W, T* FS,
-                        hipStream_t st) {
+hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule& sch, int nvar,
+                        const double* W, T* FS, hipStream_t st) {
   const bool lin = s.mode == 1;
   const T eps = (T)s.eps, th = (T)s.theta;
-  auto one = [&](const TypeDev<T>& td, auto nf_tag) -> hipError_t {
+  auto one = [&](int ntiles, int maxlen, int want, auto nf_tag) -> hipError_t {
     constexpr int NF = decltype(nf_tag)::value;
-    if (td.Nt <= 0) return hipSuccess;
-    const unsigned grid = (unsigned)((td.Nt + kReconBlock - 1) / kReconBlock);
-    const size_t shm = (size_t)td.max_tile_len * nvar * sizeof(double);
+    if (ntiles <= 0) return hipSuccess;
+    const unsigned grid = (unsigned)(want > 0 && want < ntiles ? want : ntiles);
+    const size_t shm = (size_t)maxlen * nvar * sizeof(double);
     if (lin) {
       if (nvar == 4)
-        k_recon_linear<T, NF, 4><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS);
+        k_recon<T, NF, 4, true><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
       else
-        k_recon_linear<T, NF, 1><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS);
+        k_recon<T, NF, 1, true><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
     } else {
       if (nvar == 4)
-        k_recon_weno<T, NF, 4><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS, eps, th);
+        k_recon<T, NF, 4, false><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
       else
-        k_recon_weno<T, NF, 1><<<grid, kReconBlock, shm, st>>>(W, m.N, td, FS, eps, th);
+        k_recon<T, NF, 1, false><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
     }
     return hipGetLastError();
   };
-  hipError_t e = one(m.quad, std::integral_constant<int, 4>{});
+  hipError_t e = one(m.n_tq, m.max_len_q, sch.recon_q, std::integral_constant<int, 4>{});
   if (e != hipSuccess) return e;
-  return one(m.tri, std::integral_constant<int, 3>{});
+  return one(m.n_tt, m.max_len_t, sch.recon_t, std::integral_constant<int, 3>{});
 }
 
 template <typename T>
-hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, int nvar, int mode, const T* FS,
-                       const double* W_in, const double* Wn, double* W_out, const double* dt,
-                       double* t, int* flag, int block, hipStream_t st) {
-  return grid_launch(m.N, block, [&](unsigned grid) {
+hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, const Schedule& sch, int nvar,
+                       int mode, const T* FS, const double* W_in, const double* Wn, double* W_out,
+                       const double* dt, int* flag, hipStream_t st) {
+  const int ntiles = m.n_tq + m.n_tt;
+  if (ntiles <= 0) return hipSuccess;
+  const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
 #define UW_FLUX(V, MODE) \
-  k_flux<T, V, MODE><<<grid, block, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, t, flag)
-    if (nvar == 4) {
-      switch (mode) {
-        case 0: UW_FLUX(4, 0); break;
-        case 1: UW_FLUX(4, 1); break;
-        case 2: UW_FLUX(4, 2); break;
-        default: UW_FLUX(4, 3); break;
-      }
-    } else {
-      switch (mode) {
-        case 0: UW_FLUX(1, 0); break;
-        case 1: UW_FLUX(1, 1); break;
-        case 2: UW_FLUX(1, 2); break;
-        default: UW_FLUX(1, 3); break;
-      }
+  k_flux<T, V, MODE><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag)
+  if (nvar == 4) {
+    switch (mode) {
+      case 0: UW_FLUX(4, 0); break;
+      case 1: UW_FLUX(4, 1); break;
+      case 2: UW_FLUX(4, 2); break;
+      default: UW_FLUX(4, 3); break;
     }
+  } else {
+    switch (mode) {
+      case 0: UW_FLUX(1, 0); break;
+      case 1: UW_FLUX(1, 1); break;
+      case 2: UW_FLUX(1, 2); break;
+      default: UW_FLUX(1, 3); break;
+    }
+  }
 #undef UW_FLUX
-  });
+  return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const double* W, double cfl,
                       double dt_fixed, double t_end, const double* t, double* partial,
                       double* dt, hipStream_t st) {
-  const int64_t np = cfl_partials(m.N);
-  if (dt_fixed <= 0.0) {
+  const int ntiles = m.n_tq + m.n_tt;
+  if (dt_fixed <= 0.0 && ntiles > 0) {
     if (nvar == 4)
-      k_cfl<T, 4><<<(unsigned)np, kCflBlock, 0, st>>>(m, p, W, partial);
+      k_cfl<T, 4><<<(unsigned)ntiles, kTileCells, 0, st>>>(m, p, W, partial);
     else
-      k_cfl<T, 1><<<(unsigned)np, kCflBlock, 0, st>>>(m, p, W, partial);
+      k_cfl<T, 1><<<(unsigned)ntiles, kTileCells, 0, st>>>(m, p, W, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  k_cfl_final<<<1, 1024, 0, st>>>(partial, np, cfl, dt_fixed, t_end, t, dt);
+  k_cfl_final<T><<<(unsigned)m.n_inst, 64, 0, st>>>(m, partial, cfl, dt_fixed, t_end, t, dt);
   return hipGetLastError();
 }
 
-template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, int,
-                                         const double*, double*, hipStream_t);
-template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, int,
-                                        const double*, float*, hipStream_t);
-template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, int, int,
-                                        const double*, const double*, const double*, double*,
-                                        const double*, double*, int*, int, hipStream_t);
-template hipError_t launch_flux<float>(const MeshDev<float>&, const PhysDev&, int, int,
-                                       const float*, const double*, const double*, double*,
-                                       const double*, double*, int*, int, hipStream_t);
+hipError_t launch_advance(int n_inst, double* t, const double* dt, hipStream_t st) {
+  k_advance<<<(unsigned)((n_inst + 255) / 256), 256, 0, st>>>(n_inst, t, dt);
+  return hipGetLastError();
+}
+
+template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, const Schedule&,
+                                         int, const double*, double*, hipStream_t);
+template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, const Schedule&,
+                                        int, const double*, float*, hipStream_t);
+template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, const Schedule&,
+                                        int, int, const double*, const double*, const double*,
+                                        double*, const double*, int*, hipStream_t);
+template hipError_t launch_flux<float>(const MeshDev<float>&, const PhysDev&, const Schedule&, int,
+                                       int, const float*, const double*, const double*, double*,
+                                       const double*, int*, hipStream_t);
 template hipError_t launch_cfl<double>(const MeshDev<double>&, const PhysDev&, int, const double*,
                                        double, double, double, const double*, double*, double*,
                                        hipStream_t);

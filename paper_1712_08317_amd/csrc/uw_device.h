@@ -1,4 +1,9 @@
 // Device-side table views and kernel launchers of the uweno library (internal).
+//
+// Work is organised in tiles: runs of up to kTileCells consecutive cells of
+// one cell type and one mesh instance (a single mesh is a batch of one).
+// Quadrilateral tiles come first, then triangle tiles; within each type the
+// tiles are ordered by instance.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -7,28 +12,39 @@
 
 namespace uw {
 
-// Tables of one cell type, structure of arrays [k][Nt].
-constexpr int kReconBlock = 256;   // cells per reconstruction tile (one block)
+constexpr int kTileCells = 256;   // cells per tile = threads per block
 
+struct Tile {
+  int32_t first;   // first cell (state index) of the tile
+  int32_t row0;    // its row in the tables of its cell type
+  int32_t count;   // cells in the tile (<= kTileCells)
+  int32_t inst;    // mesh instance
+};
+
+// Rows of one cell type, structure of arrays [k][Nt].
 template <typename T>
 struct TypeDev {
-  int64_t Nt = 0, first = 0;
-  const int32_t* tile_off = nullptr;   // [n_tiles + 1]
-  const int32_t* tile_ids = nullptr;   // cells staged in LDS by each tile
-  const uint16_t* lidx = nullptr;      // [S][Nt] LDS position of each slot (0 = self)
-  int32_t max_tile_len = 0;
-  const T* Y = nullptr;           // [M*4][Nt]
-  const T* off = nullptr;         // [2n*2][Nt]
-  const T* gam = nullptr;         // [2n*M][Nt]
-  const T* eta = nullptr;         // [2n*(S-1)][Nt]
+  int64_t Nt = 0;
+  const uint16_t* lidx = nullptr;   // [S][Nt] LDS position of each stencil slot (0 = the cell)
+  const T* Y = nullptr;             // [M*4][Nt] candidate operators
+  const T* off = nullptr;           // [2n*2][Nt] Gauss-point offsets (p^1, p^2)
+  const T* gam = nullptr;           // [2n*M][Nt] optimised linear weights
+  const T* eta = nullptr;           // [2n*(S-1)][Nt] point-value coefficients (linear mode)
 };
 
 template <typename T>
 struct MeshDev {
-  int64_t N = 0, Nq = 0;
+  int64_t N = 0;                    // cells of all instances
+  int32_t n_inst = 1;
+  int32_t n_tq = 0, n_tt = 0;       // quadrilateral and triangle tiles
+  const Tile* tiles = nullptr;      // [n_tq + n_tt]
+  const int32_t* tile_off = nullptr;   // [n_tq + n_tt + 1] LDS staging list offsets
+  const int32_t* tile_ids = nullptr;   // cells staged by each tile, sorted
+  int32_t max_len_q = 0, max_len_t = 0;
+  const int32_t* inst_tiles = nullptr; // [2][n_inst + 1] quad / triangle tile ranges per instance
   TypeDev<T> quad, tri;
-  const int32_t* fnb = nullptr;   // [4][N]
-  const T* fgeo = nullptr;        // [4*3][N]
+  const int32_t* fnb = nullptr;     // [4][N] (nbr << 3) | (nbr_face << 1) | left, -1 boundary
+  const T* fgeo = nullptr;          // [4*3][N] canonical normal and |l| / (2 |Omega_i|)
 };
 
 struct PhysDev {
@@ -41,27 +57,33 @@ struct SchemeDev {
   int mode;       // 0 WENO, 1 linear
 };
 
-// Face states at the Gauss points: FS[(i*8 + g)*V + v].  One block of
-// kReconBlock threads per tile.
-template <typename T>
-hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, int nvar, const double* W, T* FS,
-                        hipStream_t st);
+// Launch shape: number of persistent blocks of each kernel (0 = one block
+// per tile).
+struct Schedule {
+  int recon_q = 0, recon_t = 0, flux = 0;
+};
 
-// Flux, residual gather and RK stage.  mode 0: L = L(W_in); mode 1..3: the
-// three stages of the TVD Runge-Kutta scheme, W_out from W_in, Wn and *dt.
+// Face states at the Gauss points: FS[(i*8 + g)*V + v].
 template <typename T>
-hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, int nvar, int mode, const T* FS,
-                       const double* W_in, const double* Wn, double* W_out, const double* dt,
-                       double* t, int* flag, int block, hipStream_t st);
+hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule& sch, int nvar,
+                        const double* W, T* FS, hipStream_t st);
 
-// dt = min(cfl * min_i 1 / sum_k coef_k (|u.n_k| + c), t_end - *t) (or
-// min(dt_fixed, t_end - *t) if dt_fixed > 0), written to *dt.
+// Flux, residual gather and RK stage.  mode 0: W_out = L(W_in); mode 1..3:
+// the three stages of the TVD Runge-Kutta scheme from W_in, Wn and dt[inst].
+template <typename T>
+hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, const Schedule& sch, int nvar,
+                       int mode, const T* FS, const double* W_in, const double* Wn, double* W_out,
+                       const double* dt, int* flag, hipStream_t st);
+
+// Per instance k: dt[k] = min(cfl * min_i 1 / sum_p coef_p (|u.n_p| + c),
+// t_end - t[k]) (or min(dt_fixed, t_end - t[k]) if dt_fixed > 0); t may be
+// null (then t = 0).  partial: [n_tq + n_tt].
 template <typename T>
 hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const double* W, double cfl,
                       double dt_fixed, double t_end, const double* t, double* partial,
                       double* dt, hipStream_t st);
 
-constexpr int kCflBlock = 256;
-inline int64_t cfl_partials(int64_t N) { return (N + kCflBlock - 1) / kCflBlock; }
+// t[k] += dt[k] for every instance.
+hipError_t launch_advance(int n_inst, double* t, const double* dt, hipStream_t st);
 
 }  // namespace uw

@@ -1,0 +1,133 @@
+"""Batched stepping on the GPU: several meshes of different size and type in
+one set of launches per stage, graph-captured, each with its own time step."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import weights as ow
+from oracle import scheme as osc
+from gpu_helpers import rel_l1
+
+pytestmark = pytest.mark.gpu
+
+
+def _meshes():
+    return [
+        wl.grid_mesh(20, 20, 2.0, 2.0, "quad", 0.2, 31, True),
+        wl.grid_mesh(9, 9, 2.0, 2.0, "tri", 0.25, 32, True),
+        wl.mesh_c5(n=24, block=6, jitter=0.3, seed=33),
+        wl.grid_mesh(33, 33, 2.0, 2.0, "tri", 0.1, 34, True),
+        wl.grid_mesh(5, 5, 2.0, 2.0, "quad", 0.0, 35, True),
+    ]
+
+
+@pytest.fixture(scope="module")
+def batch_setup():
+    import torch
+    import paper_1712_08317_amd as uw
+    meshes = _meshes()
+    Ms = [uw.Mesh.from_workload(m, device=0) for m in meshes]
+    for M in Ms:
+        M.precompute()
+    states = [wl.initial_state("c2q", m, q=3) for m in meshes]
+    return uw, torch, meshes, Ms, states
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_batch_matches_single_meshes_bitwise(batch_setup, prec):
+    """Each instance of the batch takes exactly the steps the single-mesh
+    path takes, including its own CFL time step."""
+    uw, torch, meshes, Ms, states = batch_setup
+    pr = uw.UW_FP64 if prec == "fp64" else uw.UW_FP32
+    ph = uw.make_physics(uw.UW_EULER, precision=pr)
+    B = uw.Batch(Ms, ph)
+    assert B.offsets[-1] == sum(m.n_cells for m in meshes)
+    Wb = torch.from_numpy(B.to_internal(states)).to("cuda:0")
+    tb = torch.zeros(len(Ms), dtype=torch.float64, device="cuda:0")
+    B.rk3_step(Wb, tb, cfl=0.5, n_steps=3)
+    B.check()
+    got = B.to_original(Wb.cpu().numpy())
+    for k, (M, W0) in enumerate(zip(Ms, states)):
+        Wd = torch.from_numpy(M.to_internal(W0)).to("cuda:0")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        for _ in range(3):
+            M.rk3_step(ph, Wd, t, cfl=0.5)
+        ref = M.to_original(Wd.cpu().numpy())
+        assert np.array_equal(got[k], ref), k
+        assert tb[k].item() == t.item()
+    # instances of different resolution took different time steps
+    assert len(set(np.round(tb.cpu().numpy(), 15))) > 2
+
+
+def test_batch_instance_matches_oracle(batch_setup):
+    uw, torch, meshes, Ms, states = batch_setup
+    ph = uw.make_physics(uw.UW_EULER, precision=uw.UW_FP64)
+    B = uw.Batch(Ms, ph)
+    Wb = torch.from_numpy(B.to_internal(states)).to("cuda:0")
+    tb = torch.zeros(len(Ms), dtype=torch.float64, device="cuda:0")
+    dt = 2e-3
+    B.rk3_step(Wb, tb, dt_fixed=dt, n_steps=2)
+    got = B.to_original(Wb.cpu().numpy())
+    for k in (1, 2):
+        T = ow.precompute(meshes[k])
+        ref = states[k]
+        for _ in range(2):
+            ref = osc.rk3_step(T, ref, osc.Physics("euler"), dt)
+        assert rel_l1(got[k], ref) <= 1e-12
+    assert np.allclose(tb.cpu().numpy(), 2 * dt, rtol=0, atol=1e-15)
+
+
+def test_graph_replays_match_eager_steps(batch_setup):
+    """The captured graph is replayed several times, with other device work
+    and synchronisations in between; every replay equals the eager path."""
+    uw, torch, meshes, Ms, states = batch_setup
+    ph = uw.make_physics(uw.UW_EULER, precision=uw.UW_FP64)
+    B = uw.Batch(Ms, ph)
+    Wb = torch.from_numpy(B.to_internal(states)).to("cuda:0")
+    tb = torch.zeros(len(Ms), dtype=torch.float64, device="cuda:0")
+    Wref = [torch.from_numpy(M.to_internal(W)).to("cuda:0") for M, W in zip(Ms, states)]
+    tref = [torch.zeros(1, dtype=torch.float64, device="cuda:0") for _ in Ms]
+    for replay in range(4):
+        B.rk3_step(Wb, tb, cfl=0.4, n_steps=2)
+        noise = torch.randn(1000, device="cuda:0").sum()   # unrelated eager work
+        torch.cuda.synchronize()
+        del noise
+        for M, Wd, t in zip(Ms, Wref, tref):
+            for _ in range(2):
+                M.rk3_step(ph, Wd, t, cfl=0.4)
+        torch.cuda.synchronize()
+        got = B.to_original(Wb.cpu().numpy())
+        for k, M in enumerate(Ms):
+            assert np.array_equal(got[k], M.to_original(Wref[k].cpu().numpy())), (replay, k)
+
+
+def test_fp32_batch_within_1e5_of_fp64(batch_setup):
+    uw, torch, meshes, Ms, states = batch_setup
+    out = {}
+    for prec in (uw.UW_FP64, uw.UW_FP32):
+        ph = uw.make_physics(uw.UW_EULER, precision=prec)
+        B = uw.Batch(Ms, ph)
+        Wb = torch.from_numpy(B.to_internal(states)).to("cuda:0")
+        tb = torch.zeros(len(Ms), dtype=torch.float64, device="cuda:0")
+        B.rk3_step(Wb, tb, cfl=0.5, n_steps=10)
+        out[prec] = B.to_original(Wb.cpu().numpy())
+    for a, b in zip(out[uw.UW_FP32], out[uw.UW_FP64]):
+        assert rel_l1(a, b) <= 1e-5
+
+
+def test_autotune_keeps_results(batch_setup, tmp_path):
+    uw, torch, meshes, Ms, states = batch_setup
+    ph = uw.make_physics(uw.UW_EULER, precision=uw.UW_FP32)
+    B = uw.Batch(Ms, ph)
+    W0 = torch.from_numpy(B.to_internal(states)).to("cuda:0")
+    W1 = W0.clone()
+    t0 = torch.zeros(len(Ms), dtype=torch.float64, device="cuda:0")
+    t1 = t0.clone()
+    B.rk3_step(W0, t0, cfl=0.5, n_steps=2)
+    cache = str(tmp_path / "tune.txt")
+    B.autotune(ph, cache_path=cache)
+    B.autotune(ph, cache_path=cache)        # second call reads the cache
+    B.rk3_step(W1, t1, cfl=0.5, n_steps=2)
+    torch.cuda.synchronize()
+    assert torch.equal(W0, W1)
+    assert len(open(cache).read().splitlines()) == 1
