@@ -131,8 +131,10 @@ uw_status uw_mesh_export(const uw_mesh* mesh, int32_t* slots, uint8_t* present, 
 /* FP64 precompute (Sec. 3.1-3.3): scaled-frame geometry, the regularised
  * least squares of eq. (quadratic-2) for eta (eq. (polynomial-eta)), the
  * candidate operators, B and the linear weights of eq.
- * (linearweight-matrix), the optimisation of Sec. 3.3; uploads the
- * per-precision device tables on first use.  `diag` is nullable.
+ * (linearweight-matrix), the optimisation of Sec. 3.3.  Runs on the mesh's
+ * GPU (one thread per cell) or, for a host-only mesh, on host threads, with
+ * the same per-cell code.  The per-precision device tables are uploaded on
+ * first use.  `diag` is nullable.
  * Errors: UW_ESTATE (mesh not uploaded), UW_EINVAL, UW_ENOMEM, UW_EDEVICE. */
 uw_status uw_precompute_geometry(uw_mesh* mesh, const uw_scheme* scheme, uw_diag* diag);
 

@@ -14,7 +14,7 @@ LIB = os.path.join(HERE, "libuweno.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
 HOST_SOURCES = ["mesh.cpp", "precompute.cpp"]
-HIP_SOURCES = ["kernels.hip", "api.hip"]
+HIP_SOURCES = ["kernels.hip", "api.hip", "precompute_dev.hip"]
 
 HOST_FLAGS = ["-std=c++17", "-O3", "-march=x86-64-v3", "-fPIC", "-pthread",
               "-ffp-contract=off", "-Wall"]

@@ -579,9 +579,20 @@ uw_status uw_precompute_geometry(uw_mesh* m, const uw_scheme* sc, uw_diag* diag)
   m->eng.staged = Staged();
   m->eng.staged_ready = false;
   m->eng.scheme = uw::SchemeDev{sc->eps, sc->theta, sc->mode};
+  // on the mesh's GPU (one thread per cell) when it has one, else on host threads
   try {
     m->tables = uw::HostTables();
-    uw::precompute_tables(m->host, m->scheme, m->tables, uw::default_threads());
+    if (m->eng.device >= 0) {
+      std::string msg;
+      int code = 0;
+      if (!uw::precompute_tables_device(m->host, m->scheme, m->tables, m->eng.device,
+                                        uw::default_threads(), msg, code)) {
+        m->tables = uw::HostTables();
+        return fail(code == (int)hipErrorOutOfMemory ? UW_ENOMEM : UW_EDEVICE, msg);
+      }
+    } else {
+      uw::precompute_tables(m->host, m->scheme, m->tables, uw::default_threads());
+    }
   } catch (const std::bad_alloc&) {
     return fail(UW_ENOMEM, "host allocation in precompute");
   }

@@ -96,7 +96,18 @@ struct HostTables {
   int64_t n_absent = 0, n_rank_def = 0;
 };
 
+// Host precompute (threads).
 void precompute_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t, int threads);
+// The same on HIP device `device` (one thread per cell); false and a message
+// on a HIP error.
+bool precompute_tables_device(const HostMesh& m, const SchemeParams& sp, HostTables& t, int device,
+                              int threads, std::string& err, int& hip_code);
+// shared steps of both drivers
+void alloc_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t);
+void reduce_diag(const std::vector<double>& diag, const std::vector<int32_t>& counts,
+                 HostTables& t);
+void finish_tables(const HostMesh& m, HostTables& t, const std::vector<double>& normal,
+                   const std::vector<double>& length, int threads);
 
 // Tikhonov-regularised least squares operator X = (zeta I + M^T M)^{-1} M^T
 // for an m x n matrix (m >= n, row-major), through a one-sided Jacobi SVD;
