@@ -1,6 +1,7 @@
 """Benchmark: cell-stage updates per second of the WENO-3 residual inside
-SSP-RK3 steps on one MI355X, with the HBM roofline of the dominant kernel and
-the oracle timed on the host as a baseline.
+SSP-RK3 steps on one MI355X, with the roofline of the dominant kernel (the
+reconstruction, bound by FP32 vector arithmetic), the HBM fraction of the
+whole stage, and the oracle timed on the host as a baseline.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--config c5|c2q|c2t|c3|c1]
                 [--precision fp32|fp64] [--no-cpu-baseline] [--no-check]
@@ -24,6 +25,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0
+# FP32 vector peak without packed FP32 instructions: 256 CUs x 4 SIMDs x 16
+# lanes x 2.4 GHz x 2 (an FMA counts as two flops).  The published 157.3
+# TFLOP/s needs two FP32 operations per lane per cycle (packed FP32), which
+# this library does not emit.
+PEAK_FP32_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
+PEAK_FP32_PUBLISHED = 157.3
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "hbm_traffic_recon_mixed16M_fp32.md")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_1712_08317_amd", "csrc", "kernels.hip")
 
 
 def log(msg):
@@ -45,6 +54,48 @@ def recon_bytes(nf, p, nvar):
 # combination: W_in read, W_out written, W^n read in two of three stages.
 def stage_bytes(nf, p, nvar):
     return recon_bytes(nf, p, nvar) - nvar * 8 + 4 + p * 3 * nf + (8 / 3) * nvar * 8
+
+
+# Algorithmic flops of the WENO reconstruction per cell, counted on the
+# formulas of Sec. 3.4 (an add, multiply or division is one flop, a fused
+# multiply-add two, |.| none): differences to the stencil cells (S-1)V;
+# candidate gradients Y_j dW (6) and beta_j = |g_j|^2 (3) per (j, v); per
+# Gauss point and candidate the split gamma~+- = ((gamma + theta|gamma|)/2,
+# gamma~+ - gamma) (4), their sums (2) and normalisation (2), plus the two
+# reciprocals of sigma+-; per (Gauss point, j, v) the candidate value
+# d = ox gx + oy gy (3) and, for each sign, t = gamma~ beta (1), 1 + t + t^2
+# (3), beta (.) + eps (2), its square (1), alpha = gamma~ / (.)^2 (1),
+# sum alpha d (2), sum alpha (1); per (Gauss point, v) the two ratios (2),
+# the sigma scalings (2), their difference (1) and the increment (1).
+def recon_flops(nf, nvar):
+    S, M = (13, 12) if nf == 4 else (10, 9)
+    G = 2 * nf
+    per_sign = 1 + 3 + 2 + 1 + 1 + 2 + 1
+    return ((S - 1) * nvar + 9 * M * nvar + G * (8 * M + 2)
+            + G * M * nvar * (3 + 2 * per_sign) + G * nvar * 6)
+
+
+def committed_traffic():
+    """HBM bytes per reconstruction pass (both cell-type launches) from the
+    committed FETCH_SIZE / WRITE_SIZE profile, or None when the kernel source
+    has changed since the counters were taken."""
+    import hashlib
+    try:
+        text = open(TRAFFIC_PROFILE).read()
+    except OSError:
+        return None
+    fields = {}
+    for line in text.splitlines():
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    try:
+        sha = hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+        if fields.get("kernels.hip sha256") != sha:
+            return None
+        return float(fields["traffic bytes per pass"])
+    except (KeyError, ValueError, OSError):
+        return None
 
 
 def make_workload(name):
@@ -102,8 +153,8 @@ def main():
                     help="run a plain 1 GiB device copy first (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for {args.gpus}); the single-mesh path "
-              "has no multi-GPU decomposition in this build.", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs each "
+              "mesh on a single device and has no multi-GPU decomposition.", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -161,7 +212,9 @@ def main():
     value = N * 3 * args.steps / el
     rbytes = Nq * recon_bytes(4, p, nvar) + (N - Nq) * recon_bytes(3, p, nvar)
     ravg = rms / max(rn, 1) / 1e3
-    achieved = rbytes / ravg / 1e9
+    rflops = Nq * recon_flops(4, nvar) + (N - Nq) * recon_flops(3, nvar)
+    achieved = rflops / ravg / 1e12
+    hbm_achieved = rbytes / ravg / 1e9
     sbytes = Nq * stage_bytes(4, p, nvar) + (N - Nq) * stage_bytes(3, p, nvar)
 
     err = None
@@ -185,6 +238,7 @@ def main():
         base = cpu_baseline()
         log(f"cpu baseline {base['value']:.3g} cell-stage/s ({time.perf_counter() - t1:.1f} s)")
 
+    traffic = committed_traffic()
     out = {
         "metric": "cell-stage updates/s, FP32 vs FP64 at L1 err<=1e-5; % of HBM roofline",
         "value": value,
@@ -200,13 +254,20 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "cells": N, "quads": Nq, "triangles": N - Nq,
                    "state": "f64", "rk3_steps": args.steps, "cfl": 0.5},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                     "frac": achieved / PEAK_HBM_GBS, "traffic": None,
-                     "kernel": "reconstruction (k_recon_weno, both cell types)",
-                     "bytes_per_launch": rbytes, "avg_launch_ms": ravg * 1e3},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
+                     "traffic": traffic if prec == uw.UW_FP32 and nvar == 4 and args.config == "c5" else None,
+                     "kernel": "k_recon (WENO reconstruction, both cell types; one pass = "
+                               "one launch per cell type)",
+                     "flops_per_launch": rflops, "avg_launch_ms": ravg * 1e3,
+                     "peak_note": "FP32 vector without packed FP32; published 157.3",
+                     "frac_of_published": achieved / PEAK_FP32_PUBLISHED,
+                     "hbm": {"algorithmic_bytes": rbytes, "achieved_GBs": hbm_achieved,
+                             "frac": hbm_achieved / PEAK_HBM_GBS}},
         "schedule": M.schedule(),
         "stage": {"algorithmic_bytes": sbytes, "ms": el / args.steps / 3 * 1e3,
                   "achieved_GBs": sbytes / (el / args.steps / 3) / 1e9,
+                  "hbm_frac": sbytes / (el / args.steps / 3) / 1e9 / PEAK_HBM_GBS,
                   "recon_ms": ravg * 1e3, "flux_ms": fms / max(fn, 1)},
         "fp32_vs_fp64_rel_l1": err,
         "cpu_baseline": base,

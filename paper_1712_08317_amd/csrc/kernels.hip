@@ -118,8 +118,8 @@ __device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const 
 
 // WENO point values of one cell at its 2n Gauss points (paper Sec. 3.4).
 template <typename T, int NF, int V>
-__device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, int64_t i, const double* lds,
-                                 int len, T* __restrict__ FS, T eps, T theta) {
+__device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const double* lds, int len,
+                                 T* fs, T eps, T theta) {
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, G = 2 * NF;
   const int64_t n = td.Nt;
@@ -196,14 +196,14 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, int64_t i, con
       }
       R[v] = (T)w0[v] + (sp * (Np * rcp(Dp)) - sm * (Nm * rcp(Dm)));
     }
-    store_state<T, V>(FS + (i * 8 + g) * V, R);
+    store_state<T, V>(fs + g * V, R);
   }
 }
 
 // Point values of the quadratic P^2 (eq. (polynomial-eta)): the linear scheme.
 template <typename T, int NF, int V>
-__device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, int64_t i, const double* lds,
-                                   int len, T* __restrict__ FS) {
+__device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double* lds, int len,
+                                   T* fs) {
   using L = Layout<NF>;
   constexpr int S = L::S, G = 2 * NF;
   const int64_t n = td.Nt;
@@ -232,12 +232,13 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, int64_t i, c
     T R[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) R[v] = (T)w0[v] + acc[v];
-    store_state<T, V>(FS + (i * 8 + g) * V, R);
+    store_state<T, V>(fs + g * V, R);
   }
 }
 
-// Persistent reconstruction over the tiles of one cell type: each block
-// takes tiles blockIdx.x, blockIdx.x + gridDim.x, ...
+// Persistent reconstruction over the tiles of one cell type.  Dynamic LDS:
+// the staged cell averages (FP64, padded to 16 bytes), then the tile's face
+// states, written out in one coalesced block per tile.
 template <typename T, int NF, int V, bool LINEAR>
 // Occupancy measured on gfx950: the quadrilateral kernel runs fastest with
 // the whole register file (1 wave per SIMD), the triangle kernel with 2.
@@ -246,18 +247,33 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 ? 2 : 1) void
   extern __shared__ double lds[];
   const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
   const int t0 = NF == 4 ? 0 : m.n_tq, nt = NF == 4 ? m.n_tq : m.n_tt;
+  const int maxlen = NF == 4 ? m.max_len_q : m.max_len_t;
+  T* fs_lds = reinterpret_cast<T*>(lds + ((maxlen * V + 1) & ~1));
+  constexpr int REC = 8 * V;              // face-state values per cell
+  constexpr int PER = 16 / sizeof(T);     // values per 16-byte unit
+  constexpr int STRIDE = REC + PER;       // LDS row per cell, padded against bank conflicts
   for (int k = blockIdx.x; k < nt; k += gridDim.x) {
     const int tile = t0 + k;
     const Tile tl = m.tiles[tile];
     const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);
     if ((int)threadIdx.x < tl.count) {
-      const int64_t r = tl.row0 + threadIdx.x, i = tl.first + threadIdx.x;
+      const int64_t r = tl.row0 + threadIdx.x;
+      T* fs = fs_lds + threadIdx.x * STRIDE;
       if (LINEAR)
-        linear_cell<T, NF, V>(td, r, i, lds, len, FS);
+        linear_cell<T, NF, V>(td, r, lds, len, fs);
       else
-        weno_cell<T, NF, V>(td, r, i, lds, len, FS, eps, theta);
+        weno_cell<T, NF, V>(td, r, lds, len, fs, eps, theta);
     }
-    __syncthreads();   // the next tile overwrites the staged values
+    __syncthreads();
+    // the tile's face states are contiguous in FS: copy them in 16-byte units
+    constexpr int U = REC / PER;            // 16-byte units per cell
+    const int n16 = tl.count * U;
+    int4* dst = reinterpret_cast<int4*>(FS + (int64_t)tl.first * REC);
+    for (int q = threadIdx.x; q < n16; q += blockDim.x) {
+      const int c = q / U, u = q - c * U;
+      dst[q] = *reinterpret_cast<const int4*>(fs_lds + c * STRIDE + u * PER);
+    }
+    __syncthreads();   // the next tile overwrites both LDS regions
   }
 }
 
@@ -444,22 +460,28 @@ __global__ __launch_bounds__(kTileCells) void k_cfl(MeshDev<T> m, PhysDev p,
   }
 }
 
-// One wavefront per instance: the minimum over the instance's tiles.
+// One block per instance: the minimum over the instance's tiles.
+constexpr int kCflFinal = 1024;
 template <typename T>
-__global__ __launch_bounds__(64) void k_cfl_final(MeshDev<T> m, const double* __restrict__ partial,
-                                                  double cfl, double dt_fixed, double t_end,
-                                                  const double* t, double* dt) {
+__global__ __launch_bounds__(kCflFinal) void k_cfl_final(MeshDev<T> m,
+                                                         const double* __restrict__ partial,
+                                                         double cfl, double dt_fixed, double t_end,
+                                                         const double* t, double* dt) {
+  __shared__ double red[kCflFinal / 64];
   const int k = blockIdx.x;
   double x = INFINITY;
   if (dt_fixed <= 0.0) {
     const int q0 = m.inst_tiles[k], q1 = m.inst_tiles[k + 1];
     const int s0 = m.n_tq + m.inst_tiles[m.n_inst + 1 + k];
     const int s1 = m.n_tq + m.inst_tiles[m.n_inst + 1 + k + 1];
-    for (int j = q0 + threadIdx.x; j < q1; j += 64) x = fmin(x, partial[j]);
-    for (int j = s0 + threadIdx.x; j < s1; j += 64) x = fmin(x, partial[j]);
+    for (int j = q0 + threadIdx.x; j < q1; j += kCflFinal) x = fmin(x, partial[j]);
+    for (int j = s0 + threadIdx.x; j < s1; j += kCflFinal) x = fmin(x, partial[j]);
   }
   x = wave_min(x);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = x;
+  __syncthreads();
   if (threadIdx.x == 0) {
+    for (int w = 1; w < kCflFinal / 64; ++w) x = fmin(x, red[w]);
     double d = dt_fixed > 0.0 ? dt_fixed : cfl * x;
     const double rest = t_end - (t ? t[k] : 0.0);
     d = fmin(d, rest);
@@ -474,6 +496,25 @@ __global__ void k_advance(int n, double* t, const double* dt) {
 
 }  // namespace
 
+// LDS a block may allocate on the current device (queried once per device).
+size_t lds_limit() {
+  static int cache[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return 0;
+  if (dev >= 64) {
+    int v = 0;
+    return hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess
+               ? (size_t)v : 0;
+  }
+  if (cache[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess)
+      return 0;
+    cache[dev] = v;
+  }
+  return (size_t)cache[dev];
+}
+
 template <typename T>
 hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule& sch, int nvar,
                         const double* W, T* FS, hipStream_t st) {
@@ -483,7 +524,9 @@ hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule&
     constexpr int NF = decltype(nf_tag)::value;
     if (ntiles <= 0) return hipSuccess;
     const unsigned grid = (unsigned)(want > 0 && want < ntiles ? want : ntiles);
-    const size_t shm = (size_t)maxlen * nvar * sizeof(double);
+    const size_t shm = (size_t)((maxlen * nvar + 1) & ~1) * sizeof(double) +
+                       (size_t)kTileCells * (8 * nvar * sizeof(T) + 16);
+    if (shm > lds_limit()) return hipErrorInvalidConfiguration;
     if (lin) {
       if (nvar == 4)
         k_recon<T, NF, 4, true><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
@@ -543,7 +586,7 @@ hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const dou
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  k_cfl_final<T><<<(unsigned)m.n_inst, 64, 0, st>>>(m, partial, cfl, dt_fixed, t_end, t, dt);
+  k_cfl_final<T><<<(unsigned)m.n_inst, kCflFinal, 0, st>>>(m, partial, cfl, dt_fixed, t_end, t, dt);
   return hipGetLastError();
 }
 
