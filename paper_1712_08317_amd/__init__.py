@@ -270,6 +270,14 @@ class Batch:
         _check(LIB.uw_batch_rk3_step(self.handle, _ptr(W), cfl, dt_fixed, t_end, n_steps,
                                      _ptr(t_dev), _stream(stream)))
 
+    def schedule(self, set_to=None):
+        """As Mesh.schedule, for the batch's launches."""
+        got = np.zeros(3, dtype=np.int32)
+        s = None if set_to is None else np.ascontiguousarray(set_to, dtype=np.int32)
+        _check(LIB.uw_schedule(None, self.handle, got.ctypes.data,
+                               None if s is None else s.ctypes.data))
+        return tuple(int(x) for x in got)
+
     def autotune(self, physics: PhysicsC, cache_path=None, stream=None):
         _check(LIB.uw_autotune(None, self.handle, ctypes.byref(physics),
                                None if cache_path is None else cache_path.encode(),

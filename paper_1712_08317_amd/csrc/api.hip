@@ -88,6 +88,48 @@ std::vector<T> convert(const std::vector<double>& v) {
   }
 }
 
+// Face tables of the flux kernel from the FP64 face table fgeo [4*3][N]
+// (canonical normal, |l|/(2|Omega_i|)) and the pairing fnb: the normals in
+// the compute precision, [4*2][N], and the gather factors in FP64, [4][N].
+// In FP32 the rounded normals no longer close (sum_k s_k c_k n_k != 0, s_k
+// the orientation sign), which would leave a residual of FP32 size in a
+// uniform state; the factors are therefore moved by the least-norm
+// correction that restores closure for the stored normals.  In FP64 they
+// are used as computed.
+template <class T>
+void face_tables(const std::vector<double>& fgeo, const std::vector<int32_t>& fnb, int64_t N,
+                 std::vector<T>& nrm, std::vector<double>& coef) {
+  nrm.assign((size_t)8 * N, T(0));
+  coef.assign((size_t)4 * N, 0.0);
+  for (int64_t i = 0; i < N; ++i) {
+    double n[4][2], c[4], sg[4];
+    double rx = 0.0, ry = 0.0, axx = 0.0, axy = 0.0, ayy = 0.0;
+    for (int k = 0; k < 4; ++k) {
+      const T nx = (T)fgeo[(k * 3 + 0) * N + i], ny = (T)fgeo[(k * 3 + 1) * N + i];
+      nrm[(k * 2 + 0) * N + i] = nx;
+      nrm[(k * 2 + 1) * N + i] = ny;
+      n[k][0] = (double)nx;
+      n[k][1] = (double)ny;
+      c[k] = fgeo[(k * 3 + 2) * N + i];
+      const int32_t pk = fnb[k * N + i];
+      sg[k] = (pk < 0 || (pk & 1)) ? 1.0 : -1.0;
+      rx += sg[k] * c[k] * n[k][0];
+      ry += sg[k] * c[k] * n[k][1];
+      axx += n[k][0] * n[k][0];
+      axy += n[k][0] * n[k][1];
+      ayy += n[k][1] * n[k][1];
+    }
+    if constexpr (!std::is_same<T, double>::value) {
+      const double det = axx * ayy - axy * axy;
+      if (det > 0.0) {
+        const double lx = (ayy * rx - axy * ry) / det, ly = (axx * ry - axy * rx) / det;
+        for (int k = 0; k < 4; ++k) c[k] -= sg[k] * (n[k][0] * lx + n[k][1] * ly);
+      }
+    }
+    for (int k = 0; k < 4; ++k) coef[k * N + i] = c[k];
+  }
+}
+
 // Host copy of the device layout of one or more meshes (a batch), FP64.
 struct Staged {
   int64_t N = 0;
@@ -200,11 +242,11 @@ template <class T>
 struct DevTables {
   bool ready = false;
   DevBuf tiles, tile_off, tile_ids, inst_tiles, q_li, q_Y, q_off, q_gam, q_eta, t_li, t_Y, t_off,
-      t_gam, t_eta, fnb, fgeo;
+      t_gam, t_eta, fnb, fnrm, fcoef;
   uw::MeshDev<T> view;
   void reset() {
     for (DevBuf* b : {&tiles, &tile_off, &tile_ids, &inst_tiles, &q_li, &q_Y, &q_off, &q_gam,
-                      &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fgeo})
+                      &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fnrm, &fcoef})
       b->release();
     view = uw::MeshDev<T>();
     ready = false;
@@ -287,7 +329,13 @@ uw_status ensure_tables(Engine& E) {
   up(d.t_gam, convert<T>(S.t_gam));
   up(d.t_eta, convert<T>(S.t_eta));
   up(d.fnb, S.fnb);
-  up(d.fgeo, convert<T>(S.fgeo));
+  {
+    std::vector<T> nrm;
+    std::vector<double> coef;
+    face_tables<T>(S.fgeo, S.fnb, S.N, nrm, coef);
+    up(d.fnrm, nrm);
+    up(d.fcoef, coef);
+  }
   if (e == hipErrorOutOfMemory) return fail(UW_ENOMEM, "device tables: out of memory");
   if (e != hipSuccess) return hip_fail(e, "device tables upload");
   uw::MeshDev<T>& v = d.view;
@@ -314,7 +362,8 @@ uw_status ensure_tables(Engine& E) {
   v.tri.gam = d.t_gam.template as<T>();
   v.tri.eta = d.t_eta.template as<T>();
   v.fnb = d.fnb.template as<int32_t>();
-  v.fgeo = d.fgeo.template as<T>();
+  v.fnrm = d.fnrm.template as<T>();
+  v.fcoef = d.fcoef.template as<double>();
   d.ready = true;
   return UW_OK;
 }

@@ -116,22 +116,61 @@ __device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const 
   return len;
 }
 
+// Per-cell inputs of the WENO reconstruction that do not depend on the
+// state.  Latency hiding (measured on gfx950): the triangle kernel reads them
+// before the tile's staging barrier, so that their latency overlaps the
+// staging loads, and fetches each Gauss point's weights one point ahead;
+// the quadrilateral kernel, whose candidate state already fills the
+// registers of two waves per SIMD, reads them when needed (the extra live
+// registers would halve its occupancy, which costs more than it saves).
+template <int NF>
+constexpr bool kPrefetch = NF == 3;
+
+template <typename T, int NF>
+struct WenoIn {
+  int li[Layout<NF>::S];       // LDS positions of the stencil cells
+  T Y[Layout<NF>::M][4];       // candidate operators
+};
+
+template <typename T, int NF>
+__device__ inline void weno_load(const TypeDev<T>& td, int64_t r, WenoIn<T, NF>& in) {
+  using L = Layout<NF>;
+  const int64_t n = td.Nt;
+#pragma unroll
+  for (int s = 0; s < L::S; ++s) in.li[s] = td.lidx[s * n + r];
+#pragma unroll
+  for (int j = 0; j < L::M; ++j)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) in.Y[j][k] = td.Y[(j * 4 + k) * n + r];
+}
+
 // WENO point values of one cell at its 2n Gauss points (paper Sec. 3.4).
 template <typename T, int NF, int V>
-__device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const double* lds, int len,
-                                 T* fs, T eps, T theta) {
+__device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
+                                 const double* lds, int len, T* fs, T eps, T theta) {
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, G = 2 * NF;
   const int64_t n = td.Nt;
+  // the first Gauss point's weights and offsets (prefetching kernel)
+  T ga_n[M], ox_n = 0, oy_n = 0;
+  if (kPrefetch<NF>) {
+    ox_n = td.off[r];
+    oy_n = td.off[n + r];
+#pragma unroll
+    for (int j = 0; j < M; ++j) ga_n[j] = td.gam[j * n + r];
+  }
+  // per-cell inputs: prefetched, or read here
+  auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)td.lidx[s * n + r]; };
+  auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : td.Y[(j * 4 + k) * n + r]; };
   double w0[V];
-  const int l0 = td.lidx[r];
+  const int l0 = li(0);
 #pragma unroll
   for (int v = 0; v < V; ++v) w0[v] = lds[v * len + l0];
   // differences to the stencil cells, formed in FP64
   T dW[S - 1][V];
 #pragma unroll
   for (int s = 0; s < S - 1; ++s) {
-    const int l = td.lidx[(s + 1) * n + r];
+    const int l = li(s + 1);
 #pragma unroll
     for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
@@ -139,9 +178,8 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const double* 
   T gx[M][V], gy[M][V], be[M][V], bpe[M][V];
 #pragma unroll
   for (int j = 0; j < M; ++j) {
-    const T y00 = td.Y[(j * 4 + 0) * n + r], y01 = td.Y[(j * 4 + 1) * n + r];
-    const T y10 = td.Y[(j * 4 + 2) * n + r], y11 = td.Y[(j * 4 + 3) * n + r];
     const int a = L::a(j) - 1, b = L::b(j) - 1;
+    const T y00 = Y(j, 0), y01 = Y(j, 1), y10 = Y(j, 2), y11 = Y(j, 3);
 #pragma unroll
     for (int v = 0; v < V; ++v) {
       gx[j][v] = y00 * dW[a][v] + y01 * dW[b][v];
@@ -152,16 +190,32 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const double* 
   }
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
-    const T ox = td.off[(2 * g) * n + r], oy = td.off[(2 * g + 1) * n + r];
+    T ox, oy, ga[M];
+    if (kPrefetch<NF>) {
+      ox = ox_n;
+      oy = oy_n;
+#pragma unroll
+      for (int j = 0; j < M; ++j) ga[j] = ga_n[j];
+      if (g + 1 < G) {
+        ox_n = td.off[(2 * g + 2) * n + r];
+        oy_n = td.off[(2 * g + 3) * n + r];
+#pragma unroll
+        for (int j = 0; j < M; ++j) ga_n[j] = td.gam[((g + 1) * M + j) * n + r];
+      }
+    } else {
+      ox = td.off[(2 * g) * n + r];
+      oy = td.off[(2 * g + 1) * n + r];
+#pragma unroll
+      for (int j = 0; j < M; ++j) ga[j] = td.gam[(g * M + j) * n + r];
+    }
     // split of the linear weights: gamma~+ = (gamma + theta|gamma|)/2,
     // gamma~- = gamma~+ - gamma, normalised by their sums sigma+-
     T gp[M], gm[M];
     T sp = 0, sm = 0;
 #pragma unroll
     for (int j = 0; j < M; ++j) {
-      const T ga = td.gam[(g * M + j) * n + r];
-      const T tp = T(0.5) * (ga + theta * fabs(ga));
-      const T tm = tp - ga;
+      const T tp = T(0.5) * (ga[j] + theta * fabs(ga[j]));
+      const T tm = tp - ga[j];
       gp[j] = tp;
       gm[j] = tm;
       sp += tp;
@@ -255,14 +309,17 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 ? 2 : 1) void
   for (int k = blockIdx.x; k < nt; k += gridDim.x) {
     const int tile = t0 + k;
     const Tile tl = m.tiles[tile];
+    const bool act = (int)threadIdx.x < tl.count;
+    const int64_t r = tl.row0 + threadIdx.x;
+    WenoIn<T, NF> in;
+    if (!LINEAR && kPrefetch<NF> && act) weno_load<T, NF>(td, r, in);
     const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);
-    if ((int)threadIdx.x < tl.count) {
-      const int64_t r = tl.row0 + threadIdx.x;
+    if (act) {
       T* fs = fs_lds + threadIdx.x * STRIDE;
       if (LINEAR)
         linear_cell<T, NF, V>(td, r, lds, len, fs);
       else
-        weno_cell<T, NF, V>(td, r, lds, len, fs, eps, theta);
+        weno_cell<T, NF, V>(td, r, in, lds, len, fs, eps, theta);
     }
     __syncthreads();
     // the tile's face states are contiguous in FS: copy them in 16-byte units
@@ -278,10 +335,11 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 ? 2 : 1) void
 }
 
 // HLLC flux through a face with unit normal (nx, ny), left state WL, right
-// state WR: rotate into the face frame, Toro's HLLC with Davis wave speeds,
-// rotate back.
+// state WR: rotate into the face frame, Toro's HLLC with Davis wave speeds.
+// Returns the flux in the face frame (mass, normal momentum, tangential
+// momentum, energy); the caller rotates it back in FP64.
 template <typename T>
-__device__ inline void hllc(const T* WL, const T* WR, T nx, T ny, T gam, T* F) {
+__device__ inline void hllc(const T* WL, const T* WR, T nx, T ny, T gam, T* f) {
   const T rL = WL[0], rR = WR[0];
   const T irL = T(1) / rL, irR = T(1) / rR;
   const T uL = (WL[1] * nx + WL[2] * ny) * irL, vL = (-WL[1] * ny + WL[2] * nx) * irL;
@@ -293,45 +351,55 @@ __device__ inline void hllc(const T* WL, const T* WR, T nx, T ny, T gam, T* F) {
   const T SL = fmin(uL - aL, uR - aR), SR = fmax(uL + aL, uR + aR);
   const T Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
                (rL * (SL - uL) - rR * (SR - uR));
-  T f[4];
   if (T(0) <= SL) {
     f[0] = rL * uL;
     f[1] = rL * uL * uL + pL;
     f[2] = rL * uL * vL;
     f[3] = (EL + pL) * uL;
   } else if (T(0) <= Ss) {
-    const T c = rL * (SL - uL) / (SL - Ss);
-    const T e = c * (EL * irL + (Ss - uL) * (Ss + pL / (rL * (SL - uL))));
-    f[0] = rL * uL + SL * (c - rL);
-    f[1] = rL * uL * uL + pL + SL * (c * Ss - rL * uL);
-    f[2] = rL * uL * vL + SL * (c * vL - rL * vL);
-    f[3] = (EL + pL) * uL + SL * (e - EL);
+    // F*_L = F_L + S_L (U*_L - U_L), with U*_L - U_L written in terms of
+    // d = S* - u_L so that it vanishes exactly for equal states
+    const T d = Ss - uL;
+    const T cm = rL * d / (SL - Ss);   // rho*_L - rho_L
+    f[0] = rL * uL + SL * cm;
+    f[1] = rL * uL * uL + pL + SL * (cm * Ss + rL * d);
+    f[2] = rL * uL * vL + SL * (cm * vL);
+    f[3] = (EL + pL) * uL +
+           SL * (EL * irL * cm + (rL + cm) * d * (Ss + pL / (rL * (SL - uL))));
   } else if (T(0) < SR) {
-    const T c = rR * (SR - uR) / (SR - Ss);
-    const T e = c * (ER * irR + (Ss - uR) * (Ss + pR / (rR * (SR - uR))));
-    f[0] = rR * uR + SR * (c - rR);
-    f[1] = rR * uR * uR + pR + SR * (c * Ss - rR * uR);
-    f[2] = rR * uR * vR + SR * (c * vR - rR * vR);
-    f[3] = (ER + pR) * uR + SR * (e - ER);
+    const T d = Ss - uR;
+    const T cm = rR * d / (SR - Ss);   // rho*_R - rho_R
+    f[0] = rR * uR + SR * cm;
+    f[1] = rR * uR * uR + pR + SR * (cm * Ss + rR * d);
+    f[2] = rR * uR * vR + SR * (cm * vR);
+    f[3] = (ER + pR) * uR +
+           SR * (ER * irR * cm + (rR + cm) * d * (Ss + pR / (rR * (SR - uR))));
   } else {
     f[0] = rR * uR;
     f[1] = rR * uR * uR + pR;
     f[2] = rR * uR * vR;
     f[3] = (ER + pR) * uR;
   }
-  F[0] = f[0];
-  F[1] = f[1] * nx - f[2] * ny;
-  F[2] = f[1] * ny + f[2] * nx;
-  F[3] = f[3];
 }
 
+// Numerical flux through a face in the lab frame, in FP64: the HLLC flux is
+// evaluated in the compute precision in the face frame and rotated back with
+// the stored normal in FP64, so that a uniform state, whose face fluxes are
+// then exactly p n (and 0), leaves a residual of FP64 size only.
 template <typename T, int V>
-__device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const PhysDev& p, T* F) {
+__device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const PhysDev& p,
+                                 double* F) {
   if constexpr (V == 4) {
-    hllc<T>(WL, WR, nx, ny, (T)p.gamma, F);
+    T f[4];
+    hllc<T>(WL, WR, nx, ny, (T)p.gamma, f);
+    const double x = nx, y = ny, f1 = f[1], f2 = f[2];
+    F[0] = f[0];
+    F[1] = f1 * x - f2 * y;
+    F[2] = f1 * y + f2 * x;
+    F[3] = f[3];
   } else {
-    const T an = (T)p.ax * nx + (T)p.ay * ny;
-    F[0] = an >= T(0) ? an * WL[0] : an * WR[0];
+    const double an = p.ax * (double)nx + p.ay * (double)ny;
+    F[0] = an * (double)(an >= 0.0 ? WL[0] : WR[0]);
   }
 }
 
@@ -347,15 +415,15 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
     if ((int)threadIdx.x >= tl.count) continue;
     const int64_t i = tl.first + threadIdx.x;
     const int nf = tile < m.n_tq ? 4 : 3;
-    T acc[V];
+    double acc[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = 0;
+    for (int v = 0; v < V; ++v) acc[v] = 0.0;
     bool bad = false;
     for (int k = 0; k < nf; ++k) {
       const int32_t pk = m.fnb[k * N + i];
-      const T nx = m.fgeo[(k * 3 + 0) * N + i];
-      const T ny = m.fgeo[(k * 3 + 1) * N + i];
-      const T coef = m.fgeo[(k * 3 + 2) * N + i];
+      const T nx = m.fnrm[(k * 2 + 0) * N + i];
+      const T ny = m.fnrm[(k * 2 + 1) * N + i];
+      const double coef = m.fcoef[k * N + i];
       T o0[V], o1[V], t0[V], t1[V];
       load_state<T, V>(FS + (i * 8 + 2 * k) * V, o0);
       load_state<T, V>(FS + (i * 8 + 2 * k + 1) * V, o1);
@@ -375,7 +443,7 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
         load_state<T, V>(FS + (c * 8 + 2 * kp) * V, t1);
       }
       if constexpr (V == 4) bad |= !(o0[0] > T(0)) || !(o1[0] > T(0));
-      T F0[V], F1[V];
+      double F0[V], F1[V];
       if (left) {
         face_flux<T, V>(o0, t0, nx, ny, p, F0);
         face_flux<T, V>(o1, t1, nx, ny, p, F1);
@@ -383,7 +451,7 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
         face_flux<T, V>(t0, o0, nx, ny, p, F0);
         face_flux<T, V>(t1, o1, nx, ny, p, F1);
       }
-      const T sc = left ? coef : -coef;
+      const double sc = left ? coef : -coef;
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] += sc * (F0[v] + F1[v]);
     }
@@ -391,7 +459,7 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
     if (MODE != 0) dt = dtp[tl.inst];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
-      const double Lv = -(double)acc[v];
+      const double Lv = -acc[v];
       double out;
       if (MODE == 0) {
         out = Lv;
@@ -443,8 +511,8 @@ __global__ __launch_bounds__(kTileCells) void k_cfl(MeshDev<T> m, PhysDev p,
     const int nf = tile < m.n_tq ? 4 : 3;
     double s = 0.0;
     for (int k = 0; k < nf; ++k) {
-      const double nx = m.fgeo[(k * 3 + 0) * N + i], ny = m.fgeo[(k * 3 + 1) * N + i];
-      const double coef = m.fgeo[(k * 3 + 2) * N + i];
+      const double nx = m.fnrm[(k * 2 + 0) * N + i], ny = m.fnrm[(k * 2 + 1) * N + i];
+      const double coef = m.fcoef[k * N + i];
       s += coef * (fabs(u * nx + v * ny) + c);
     }
     x = 1.0 / s;

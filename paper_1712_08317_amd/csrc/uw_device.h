@@ -44,7 +44,8 @@ struct MeshDev {
   const int32_t* inst_tiles = nullptr; // [2][n_inst + 1] quad / triangle tile ranges per instance
   TypeDev<T> quad, tri;
   const int32_t* fnb = nullptr;     // [4][N] (nbr << 3) | (nbr_face << 1) | left, -1 boundary
-  const T* fgeo = nullptr;          // [4*3][N] canonical normal and |l| / (2 |Omega_i|)
+  const T* fnrm = nullptr;          // [4*2][N] canonical unit normal of each face
+  const double* fcoef = nullptr;    // [4][N] |l| / (2 |Omega_i|), closed for the stored normals
 };
 
 struct PhysDev {
