@@ -14,7 +14,18 @@ Paper:
   with weights 1/2, eq. (transform) rotation to the face frame, HLLC flux.
 * Sec. 4: the three-stage TVD Runge-Kutta scheme.
 
+* Sec. 4 (Euler systems): the reconstruction may be carried out on the
+  characteristic variables U = R^-1 W of Roe's mean matrix
+  n_x dF/dW + n_y dG/dW at the quadrature point, the reconstructed values
+  being projected back with R.
+
 Readings:
+* characteristic variables: the Roe mean is taken between the two cells
+  that share the face of the quadrature point (cell averages; a boundary
+  face uses the cell itself), with that face's outward normal; both points
+  of a face share the projection.  The candidate polynomials, their
+  smoothness indicators and the point values are all projected, and the
+  nonlinear weights are formed per characteristic field;
 * the final reconstruction keeps the factors sigma^pm of the split form and
   is evaluated about W_i0: R = W_i0 + sigma^+ sum delta^+ (P_j - W_i0)
   - sigma^- sum delta^- (P_j - W_i0) (equal to the split form because
@@ -54,10 +65,75 @@ class Physics:
 
 
 # --------------------------------------------------------------------------
+# characteristic decomposition (Sec. 4, Euler systems)
+# --------------------------------------------------------------------------
+
+def roe_average(WL, WR, gamma):
+    """Roe's mean state of two conserved states (leading axis = variables):
+    density-weighted velocity and total enthalpy, and the sound speed."""
+    rL, rR = WL[0], WR[0]
+    uL, vL = WL[1] / rL, WL[2] / rL
+    uR, vR = WR[1] / rR, WR[2] / rR
+    pL = (gamma - 1.0) * (WL[3] - 0.5 * rL * (uL * uL + vL * vL))
+    pR = (gamma - 1.0) * (WR[3] - 0.5 * rR * (uR * uR + vR * vR))
+    HL, HR = (WL[3] + pL) / rL, (WR[3] + pR) / rR
+    sL, sR = np.sqrt(rL), np.sqrt(rR)
+    u = (sL * uL + sR * uR) / (sL + sR)
+    v = (sL * vL + sR * vR) / (sL + sR)
+    H = (sL * HL + sR * HR) / (sL + sR)
+    c = np.sqrt((gamma - 1.0) * (H - 0.5 * (u * u + v * v)))
+    return u, v, H, c
+
+
+def eigenvectors(u, v, H, c, nx, ny, gamma):
+    """Right eigenvectors (columns of R) and left eigenvectors (rows of
+    R^-1) of n_x dF/dW + n_y dG/dW for the 2D Euler equations at the state
+    (u, v, H, c); eigenvalues u.n - c, u.n, u.n, u.n + c.  Returns
+    (R, Rinv, lam) with shapes [..., 4, 4], [..., 4, 4], [..., 4]."""
+    un = u * nx + v * ny
+    ut = -u * ny + v * nx
+    q2 = 0.5 * (u * u + v * v)
+    one, zero = np.ones_like(u), np.zeros_like(u)
+    R = np.stack([
+        np.stack([one, u - c * nx, v - c * ny, H - c * un], -1),
+        np.stack([one, u, v, q2], -1),
+        np.stack([zero, -ny * one, nx * one, ut], -1),
+        np.stack([one, u + c * nx, v + c * ny, H + c * un], -1),
+    ], -1)                                                   # columns are eigenvectors
+    b1 = (gamma - 1.0) / (c * c)
+    b2 = q2 * b1
+    Rinv = np.stack([
+        np.stack([0.5 * (b2 + un / c), 0.5 * (-b1 * u - nx / c), 0.5 * (-b1 * v - ny / c),
+                  0.5 * b1], -1),
+        np.stack([1.0 - b2, b1 * u, b1 * v, -b1], -1),
+        np.stack([-ut, -ny * one, nx * one, zero], -1),
+        np.stack([0.5 * (b2 - un / c), 0.5 * (-b1 * u + nx / c), 0.5 * (-b1 * v + ny / c),
+                  0.5 * b1], -1),
+    ], -2)                                                   # rows are left eigenvectors
+    lam = np.stack([un - c, un, un, un + c], -1)
+    return R, Rinv, lam
+
+
+# --------------------------------------------------------------------------
 # reconstruction (WENO or linear) at the Gauss points of a group of cells
 # --------------------------------------------------------------------------
 
-def _weno_group(g, W, scheme, rows):
+def _nonlinear_combination(gp, sp, gm, sm, beta, d, eps):
+    """sum over signs of sign sigma^pm sum_j delta_j^pm d_j, with the new
+    smoothness indicator of Sec. 3.4.  gp, gm: [m,G,M] normalised split
+    weights; sp, sm: [m,G,1] their sums; beta: [F,m,G,M] indicators;
+    d: [F,m,G,M] candidate increments P_j(x_G) - W_i0 (F fields)."""
+    out = 0.0
+    for gw, sig, sgn in ((gp, sp, 1.0), (gm, sm, -1.0)):
+        t = gw[None] * beta
+        bt = beta * (1.0 + t + t * t)
+        alpha = gw[None] / (bt + eps) ** 2
+        delta = alpha / alpha.sum(axis=-1, keepdims=True)
+        out = out + sgn * sig[None, :, :, 0] * (delta * d).sum(axis=-1)
+    return out                                          # [F,m,G]
+
+
+def _weno_group(g, W, scheme, rows, gamma=1.4):
     st = g.st
     cells = st.cells[rows]
     rc = st.runtime_cell[rows]                          # [m,S]
@@ -82,20 +158,28 @@ def _weno_group(g, W, scheme, rows):
     sm = tm.sum(axis=-1, keepdims=True)
     gp = tp / sp
     gm = tm / sm
+    G = gam.shape[1]
     # P_j(x_G) - W_i0 at every point: [V,m,G,M]
     d = off[None, :, :, None, 0] * gx[:, :, None, :] + off[None, :, :, None, 1] * gy[:, :, None, :]
-    b = beta[:, :, None, :]
-    out = W0[:, :, None].copy()
-    for gw, sig, sgn in ((gp, sp, 1.0), (gm, sm, -1.0)):
-        t = gw[None] * b
-        bt = b * (1.0 + t + t * t)
-        alpha = gw[None] / (bt + scheme.eps) ** 2
-        delta = alpha / alpha.sum(axis=-1, keepdims=True)
-        out = out + sgn * sig[None, :, :, 0] * (delta * d).sum(axis=-1)
-    return out                                          # [V,m,G]
+    if scheme.variables == "characteristic" and W.shape[0] == 4:
+        # projection of each Gauss point: Roe mean of the cell and the
+        # neighbour across the point's face, with that face's normal
+        face = np.arange(G) // 2
+        nbr = rc[:, 1 + face]                           # [m,G]
+        u, v, H, c = roe_average(W0[:, :, None], W[:, nbr], gamma)
+        nrm = g.normal[rows][:, face]                   # [m,G,2]
+        Rm, Li, _ = eigenvectors(u, v, H, c, nrm[..., 0], nrm[..., 1], gamma)   # [m,G,4,4]
+        dc = np.einsum("mgcv,vmgj->cmgj", Li, d)
+        gxc = np.einsum("mgcv,vmj->cmgj", Li, gx)
+        gyc = np.einsum("mgcv,vmj->cmgj", Li, gy)
+        inc = _nonlinear_combination(gp, sp, gm, sm, gxc * gxc + gyc * gyc, dc, scheme.eps)
+        return W0[:, :, None] + np.einsum("mgvc,cmg->vmg", Rm, inc)
+    inc = _nonlinear_combination(gp, sp, gm, sm, np.broadcast_to(beta[:, :, None, :], d.shape),
+                                 d, scheme.eps)
+    return W0[:, :, None] + inc                         # [V,m,G]
 
 
-def reconstruct_face_states(tables: Tables, W, cells=None):
+def reconstruct_face_states(tables: Tables, W, cells=None, gamma=1.4):
     """Reconstructed values at the 2n Gauss points of each requested cell.
 
     Returns a dict cell -> array [V, 2n] (point g = 2k + q is the q-th Gauss
@@ -113,7 +197,7 @@ def reconstruct_face_states(tables: Tables, W, cells=None):
         rows = (tables.loc[mine] & 0xFFFFFFFF).astype(np.int64)
         step = 8192
         for i in range(0, rows.size, step):
-            R = _weno_group(g, W, tables.scheme, rows[i:i + step])
+            R = _weno_group(g, W, tables.scheme, rows[i:i + step], gamma)
             for c, r in zip(mine[i:i + step], np.moveaxis(R, 1, 0)):
                 out[int(c)] = r
     return out
@@ -194,7 +278,7 @@ def residual(tables: Tables, W, physics: Physics, cells=None):
     cells = np.asarray(cells, dtype=np.int64)
     nb = conn.nbr[cells]
     need = np.unique(np.concatenate([cells, nb[nb >= 0]]))
-    R = reconstruct_face_states(tables, W, need)
+    R = reconstruct_face_states(tables, W, need, physics.gamma)
     V = W.shape[0]
     L = np.zeros((V, cells.size))
     for idx, i in enumerate(cells):
@@ -245,7 +329,8 @@ def residual_vectorized(tables: Tables, W, physics: Physics):
         step = 8192
         for i in range(0, cells.size, step):
             rows = np.arange(i, min(cells.size, i + step))
-            R[:, cells[rows], :2 * nf_value] = _weno_group(g, W, tables.scheme, rows)
+            R[:, cells[rows], :2 * nf_value] = _weno_group(g, W, tables.scheme, rows,
+                                                           physics.gamma)
         normal[cells] = g.normal
         length[cells] = g.length
         area[cells] = g.area

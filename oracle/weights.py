@@ -45,6 +45,7 @@ class Scheme:
     optimize: bool = True
     d_scope: str = "gp"       # "gp": d per Gauss point; "cell": from max over the cell's points
     mode: str = "weno"        # "weno" or "linear"
+    variables: str = "conserved"   # "conserved" or "characteristic" (Euler only)
 
 
 RANK_TOL = 1e-12
