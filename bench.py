@@ -67,12 +67,20 @@ def stage_bytes(nf, p, nvar):
 # (3), beta (.) + eps (2), its square (1), alpha = gamma~ / (.)^2 (1),
 # sum alpha d (2), sum alpha (1); per (Gauss point, v) the two ratios (2),
 # the sigma scalings (2), their difference (1) and the increment (1).
-def recon_flops(nf, nvar):
+#
+# Characteristic variables (Sec. 4, Euler): per face the Roe mean and the two
+# eigenvector matrices (80, counting a square root or division as one), per
+# face and field the projected differences (S-1) x 7, gradients, indicators
+# and eps (10 per candidate); per Gauss point the projection back (4 x 8).
+def recon_flops(nf, nvar, characteristic=False):
     S, M = (13, 12) if nf == 4 else (10, 9)
     G = 2 * nf
     per_sign = 1 + 3 + 2 + 1 + 1 + 2 + 1
-    return ((S - 1) * nvar + 9 * M * nvar + G * (8 * M + 2)
-            + G * M * nvar * (3 + 2 * per_sign) + G * nvar * 6)
+    common = G * (8 * M + 2) + G * M * nvar * (3 + 2 * per_sign) + G * nvar * 6
+    if characteristic and nvar == 4:
+        return ((S - 1) * nvar + common + nf * (80 + nvar * ((S - 1) * 7 + 10 * M))
+                + G * nvar * 8)
+    return (S - 1) * nvar + 9 * M * nvar + common
 
 
 def l1_errors(a, b):
@@ -233,6 +241,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="c5")
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp64"])
+    ap.add_argument("--variables", default="conserved", choices=["conserved", "characteristic"],
+                    help="reconstruct the conserved or the characteristic variables (Euler)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 reference run")
     ap.add_argument("--copy-probe", action="store_true",
@@ -257,7 +267,9 @@ def main():
     M = uw.Mesh.from_workload(mesh, device=0)
     log(f"upload/connectivity/stencils {time.perf_counter() - t1:.1f} s")
     t1 = time.perf_counter()
-    diag = M.precompute()
+    char = args.variables == "characteristic"
+    diag = M.precompute(uw.make_scheme(
+        variables=uw.UW_CHARACTERISTIC if char else uw.UW_CONSERVED))
     log(f"FP64 precompute {time.perf_counter() - t1:.1f} s; max|gamma| raw "
         f"{diag['max_abs_gamma_raw']:.3g} opt {diag['max_abs_gamma_opt']:.3g}")
     eq = uw.UW_ADVECTION if cname == "c1" else uw.UW_EULER
@@ -301,7 +313,7 @@ def main():
     value = N * 3 * args.steps / el
     rbytes = Nq * recon_bytes(4, p, nvar) + (N - Nq) * recon_bytes(3, p, nvar)
     ravg = rms / max(rn, 1) / 1e3
-    rflops = Nq * recon_flops(4, nvar) + (N - Nq) * recon_flops(3, nvar)
+    rflops = Nq * recon_flops(4, nvar, char) + (N - Nq) * recon_flops(3, nvar, char)
     achieved = rflops / ravg / 1e12
     hbm_achieved = rbytes / ravg / 1e9
     sbytes = Nq * stage_bytes(4, p, nvar) + (N - Nq) * stage_bytes(3, p, nvar)
@@ -342,10 +354,12 @@ def main():
         "dtype": "f32" if prec == uw.UW_FP32 else "f64",
         "data": "synthetic",
         "config": {"workload": desc, "cells": N, "quads": Nq, "triangles": N - Nq,
-                   "state": "f64", "rk3_steps": args.steps, "cfl": 0.5},
+                   "state": "f64", "rk3_steps": args.steps, "cfl": 0.5,
+                   "variables": args.variables},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_FP32_TFLOPS,
-                     "traffic": traffic if prec == uw.UW_FP32 and nvar == 4 and args.config == "c5" else None,
+                     "traffic": (traffic if prec == uw.UW_FP32 and nvar == 4 and args.config == "c5"
+                                 and not char else None),
                      "kernel": "k_recon (WENO reconstruction, both cell types; one pass = "
                                "one launch per cell type)",
                      "flops_per_launch": rflops, "avg_launch_ms": ravg * 1e3,

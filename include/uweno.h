@@ -45,6 +45,7 @@ typedef enum {
 
 enum { UW_BC_PERIODIC = 0, UW_BC_TRANSMISSIVE = 1 };
 enum { UW_WENO = 0, UW_LINEAR = 1 };
+enum { UW_CONSERVED = 0, UW_CHARACTERISTIC = 1 };
 enum { UW_D_PER_GP = 0, UW_D_PER_CELL = 1 };
 enum { UW_ADVECTION = 0, UW_EULER = 1 };
 enum { UW_FP64 = 0, UW_FP32 = 1 };   /* UW_FP32: FP32 arithmetic, FP64 state */
@@ -76,10 +77,14 @@ typedef struct {
  * given by the paper; 1e-3), optimize = apply the linear-weight optimisation
  * of Sec. 3.3 (1), d_scope = UW_D_PER_GP (weights d from each Gauss point's
  * own linear weights) or UW_D_PER_CELL, mode = UW_WENO or UW_LINEAR (the
- * quadratic P^2 of eq. (polynomial-eta) at the Gauss points). */
+ * quadratic P^2 of eq. (polynomial-eta) at the Gauss points), variables =
+ * UW_CONSERVED (component-wise) or UW_CHARACTERISTIC (Euler only; Sec. 4:
+ * WENO on the characteristic variables of Roe's mean matrix between the
+ * cell and the neighbour across each face, projected back; ignored for
+ * scalar advection and in UW_LINEAR mode).  Any other value: UW_EINVAL. */
 typedef struct {
   double zeta, theta, eps;
-  int32_t optimize, d_scope, mode;
+  int32_t optimize, d_scope, mode, variables;
 } uw_scheme;
 
 /* Physics: equation = UW_ADVECTION (u_t + ax u_x + ay u_y = 0, upwind flux)

@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("UWENO_LIB", os.path.join(HERE, "libuweno.so"))
 UW_OK, UW_EINVAL, UW_EMESH, UW_ESTATE, UW_ENOMEM, UW_EDEVICE, UW_ENONFINITE = range(7)
 UW_BC_PERIODIC, UW_BC_TRANSMISSIVE = 0, 1
 UW_WENO, UW_LINEAR = 0, 1
+UW_CONSERVED, UW_CHARACTERISTIC = 0, 1
 UW_D_PER_GP, UW_D_PER_CELL = 0, 1
 UW_ADVECTION, UW_EULER = 0, 1
 UW_FP64, UW_FP32 = 0, 1
@@ -41,7 +42,8 @@ class MeshDesc(ctypes.Structure):
 
 class SchemeC(ctypes.Structure):
     _fields_ = [("zeta", ctypes.c_double), ("theta", ctypes.c_double), ("eps", ctypes.c_double),
-                ("optimize", ctypes.c_int32), ("d_scope", ctypes.c_int32), ("mode", ctypes.c_int32)]
+                ("optimize", ctypes.c_int32), ("d_scope", ctypes.c_int32), ("mode", ctypes.c_int32),
+                ("variables", ctypes.c_int32)]
 
 
 class PhysicsC(ctypes.Structure):
@@ -124,8 +126,8 @@ def _stream(stream):
 
 
 def make_scheme(zeta=1e-14, theta=3.0, eps=1e-3, optimize=True, d_scope=UW_D_PER_GP,
-                mode=UW_WENO) -> SchemeC:
-    return SchemeC(zeta, theta, eps, int(optimize), d_scope, mode)
+                mode=UW_WENO, variables=UW_CONSERVED) -> SchemeC:
+    return SchemeC(zeta, theta, eps, int(optimize), d_scope, mode, variables)
 
 
 def make_physics(equation=UW_EULER, ax=1.0, ay=1.0, gamma=1.4, precision=UW_FP64) -> PhysicsC:

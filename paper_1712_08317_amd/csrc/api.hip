@@ -257,7 +257,7 @@ struct DevTables {
 // (uploaded on first use), work buffers, launch schedule and timing.
 struct Engine {
   int device = 0;
-  uw::SchemeDev scheme{1e-3, 3.0, 0};
+  uw::SchemeDev scheme{1e-3, 3.0, 0, 0};
   Staged staged;
   bool staged_ready = false;
   DevTables<double> d64;
@@ -422,7 +422,7 @@ uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, co
   const bool prof = timed && E.profiling;
   hipEvent_t a = nullptr, b = nullptr;
   if (prof) UW_HIP(ev_begin(E, st, &a, &b));
-  hipError_t e = uw::launch_recon<T>(d.view, E.scheme, E.sched, nvar, W_in, FS, st);
+  hipError_t e = uw::launch_recon<T>(d.view, E.scheme, phys_dev(p), E.sched, nvar, W_in, FS, st);
   if (e != hipSuccess) return hip_fail(e, "reconstruction launch");
   if (prof) {
     UW_HIP(hipEventRecord(b, st));
@@ -505,6 +505,8 @@ uw_status check_scheme(const uw_scheme* sc) {
   if (!(sc->zeta >= 0.0) || !(sc->eps > 0.0) || !(sc->theta >= 1.0))
     return fail(UW_EINVAL, "scheme needs zeta >= 0, eps > 0, theta >= 1");
   if (sc->mode != UW_WENO && sc->mode != UW_LINEAR) return fail(UW_EINVAL, "scheme.mode");
+  if (sc->variables != UW_CONSERVED && sc->variables != UW_CHARACTERISTIC)
+    return fail(UW_EINVAL, "scheme.variables");
   if (sc->d_scope != UW_D_PER_GP && sc->d_scope != UW_D_PER_CELL)
     return fail(UW_EINVAL, "scheme.d_scope");
   return UW_OK;
@@ -627,7 +629,7 @@ uw_status uw_precompute_geometry(uw_mesh* m, const uw_scheme* sc, uw_diag* diag)
   m->eng.reset_device();
   m->eng.staged = Staged();
   m->eng.staged_ready = false;
-  m->eng.scheme = uw::SchemeDev{sc->eps, sc->theta, sc->mode};
+  m->eng.scheme = uw::SchemeDev{sc->eps, sc->theta, sc->mode, sc->variables};
   // on the mesh's GPU (one thread per cell) when it has one, else on host threads
   try {
     m->tables = uw::HostTables();
@@ -740,7 +742,8 @@ uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* p
     if (m->eng.device < 0 || m->eng.device != meshes[0]->eng.device)
       return fail(UW_EINVAL, "batch meshes must live on one device");
     if (m->scheme.mode != meshes[0]->scheme.mode || m->scheme.eps != meshes[0]->scheme.eps ||
-        m->scheme.theta != meshes[0]->scheme.theta)
+        m->scheme.theta != meshes[0]->scheme.theta ||
+        m->eng.scheme.vars != meshes[0]->eng.scheme.vars)
       return fail(UW_EINVAL, "batch meshes must share one scheme");
     hm.push_back(&m->host);
     ht.push_back(&m->tables);
@@ -802,7 +805,7 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
   char key[200];
   std::snprintf(key, sizeof(key), "%lld %d %d %d %d %d %d", (long long)E.staged.N,
                 E.staged.n_inst, E.staged.n_tq, E.staged.n_tt, nvar, p->precision,
-                E.scheme.mode);
+                E.scheme.mode + 2 * E.scheme.vars);
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[320];

@@ -254,6 +254,156 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
   }
 }
 
+// Eigenvectors of Roe's mean matrix n_x dF/dW + n_y dG/dW (Euler, Sec. 4) for
+// the mean of WA and WB: right eigenvectors as columns of Rm, left ones as
+// rows of Lm, fields ordered u.n - c, u.n (entropy), u.n (shear), u.n + c.
+template <typename T>
+__device__ inline void roe_eigen(const T* WA, const T* WB, T nx, T ny, T gam, T (&Rm)[4][4],
+                                 T (&Lm)[4][4]) {
+  const T sA = sqrt(WA[0]), sB = sqrt(WB[0]);
+  const T iA = T(1) / WA[0], iB = T(1) / WB[0];
+  const T uA = WA[1] * iA, vA = WA[2] * iA, uB = WB[1] * iB, vB = WB[2] * iB;
+  const T pA = (gam - T(1)) * (WA[3] - T(0.5) * WA[0] * (uA * uA + vA * vA));
+  const T pB = (gam - T(1)) * (WB[3] - T(0.5) * WB[0] * (uB * uB + vB * vB));
+  const T HA = (WA[3] + pA) * iA, HB = (WB[3] + pB) * iB;
+  const T iw = T(1) / (sA + sB);
+  const T u = (sA * uA + sB * uB) * iw, v = (sA * vA + sB * vB) * iw;
+  const T H = (sA * HA + sB * HB) * iw;
+  const T q2 = T(0.5) * (u * u + v * v);
+  const T c = sqrt((gam - T(1)) * (H - q2)), ic = T(1) / c;
+  const T un = u * nx + v * ny, ut = -u * ny + v * nx;
+  const T b1 = (gam - T(1)) * ic * ic, b2 = q2 * b1;
+  Rm[0][0] = 1;          Rm[0][1] = 1; Rm[0][2] = 0;   Rm[0][3] = 1;
+  Rm[1][0] = u - c * nx; Rm[1][1] = u; Rm[1][2] = -ny; Rm[1][3] = u + c * nx;
+  Rm[2][0] = v - c * ny; Rm[2][1] = v; Rm[2][2] = nx;  Rm[2][3] = v + c * ny;
+  Rm[3][0] = H - c * un; Rm[3][1] = q2; Rm[3][2] = ut; Rm[3][3] = H + c * un;
+  Lm[0][0] = T(0.5) * (b2 + un * ic);
+  Lm[0][1] = T(0.5) * (-b1 * u - nx * ic);
+  Lm[0][2] = T(0.5) * (-b1 * v - ny * ic);
+  Lm[0][3] = T(0.5) * b1;
+  Lm[1][0] = T(1) - b2; Lm[1][1] = b1 * u; Lm[1][2] = b1 * v; Lm[1][3] = -b1;
+  Lm[2][0] = -ut;       Lm[2][1] = -ny;    Lm[2][2] = nx;     Lm[2][3] = 0;
+  Lm[3][0] = T(0.5) * (b2 - un * ic);
+  Lm[3][1] = T(0.5) * (-b1 * u + nx * ic);
+  Lm[3][2] = T(0.5) * (-b1 * v + ny * ic);
+  Lm[3][3] = T(0.5) * b1;
+}
+
+// WENO point values of one cell reconstructed in characteristic variables
+// (Sec. 4, Euler): per face, the projection of Roe's mean matrix between the
+// cell and the face neighbour, with the cell's outward normal; the stencil
+// differences are projected one field at a time, the candidate gradients,
+// indicators and nonlinear weights are formed per field, and the two Gauss
+// points of the face are projected back.
+template <typename T, int NF>
+__device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
+                                      const double* lds, int len, const T (&nrm)[NF][2], T* fs,
+                                      T eps, T theta, T gam) {
+  using L = Layout<NF>;
+  constexpr int S = L::S, M = L::M, V = 4;
+  const int64_t n = td.Nt;
+  auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)td.lidx[s * n + r]; };
+  auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : td.Y[(j * 4 + k) * n + r]; };
+  double w0[V];
+  const int l0 = li(0);
+#pragma unroll
+  for (int v = 0; v < V; ++v) w0[v] = lds[v * len + l0];
+  T W0[V];
+#pragma unroll
+  for (int v = 0; v < V; ++v) W0[v] = (T)w0[v];
+  T dW[S - 1][V];
+#pragma unroll
+  for (int s = 0; s < S - 1; ++s) {
+    const int l = li(s + 1);
+#pragma unroll
+    for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
+  }
+#pragma unroll 1
+  for (int k = 0; k < NF; ++k) {
+    // Roe mean of the cell and the neighbour across face k (slot k + 1)
+    T Rm[4][4], Lm[4][4], Wk[V];
+    {
+      const int l = li(k + 1);
+#pragma unroll
+      for (int v = 0; v < V; ++v) Wk[v] = (T)lds[v * len + l];
+    }
+    roe_eigen<T>(W0, Wk, nrm[k][0], nrm[k][1], gam, Rm, Lm);
+    // split linear weights of the face's two Gauss points
+    T gp[2][M], gm[2][M], sp[2], sm[2], ox[2], oy[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int g = 2 * k + q;
+      ox[q] = td.off[(2 * g) * n + r];
+      oy[q] = td.off[(2 * g + 1) * n + r];
+      sp[q] = 0;
+      sm[q] = 0;
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const T ga = td.gam[(g * M + j) * n + r];
+        const T tp = T(0.5) * (ga + theta * fabs(ga));
+        gp[q][j] = tp;
+        gm[q][j] = tp - ga;
+        sp[q] += tp;
+        sm[q] += tp - ga;
+      }
+      const T rp = rcp(sp[q]), rm = rcp(sm[q]);
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        gp[q][j] *= rp;
+        gm[q][j] *= rm;
+      }
+    }
+    T inc[2][V];   // reconstructed increments per field at the two points
+#pragma unroll
+    for (int c = 0; c < V; ++c) {
+      // field c of the stencil differences, then its candidate gradients
+      T dc[S - 1];
+#pragma unroll
+      for (int s = 0; s < S - 1; ++s)
+        dc[s] = Lm[c][0] * dW[s][0] + Lm[c][1] * dW[s][1] + Lm[c][2] * dW[s][2] +
+                Lm[c][3] * dW[s][3];
+      T gx[M], gy[M], be[M], bpe[M];
+#pragma unroll
+      for (int j = 0; j < M; ++j) {
+        const int a = L::a(j) - 1, b = L::b(j) - 1;
+        gx[j] = Y(j, 0) * dc[a] + Y(j, 1) * dc[b];
+        gy[j] = Y(j, 2) * dc[a] + Y(j, 3) * dc[b];
+        be[j] = gx[j] * gx[j] + gy[j] * gy[j];
+        bpe[j] = be[j] + eps;
+      }
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        T Np = 0, Dp = 0, Nm = 0, Dm = 0;
+#pragma unroll
+        for (int j = 0; j < M; ++j) {
+          const T d = fma(ox[q], gx[j], oy[q] * gy[j]);
+          const T b = be[j];
+          T t = gp[q][j] * b;
+          T qq = fma(b, fma(t, t, t), bpe[j]);
+          T al = gp[q][j] * rcp(qq * qq);
+          Dp += al;
+          Np = fma(al, d, Np);
+          t = gm[q][j] * b;
+          qq = fma(b, fma(t, t, t), bpe[j]);
+          al = gm[q][j] * rcp(qq * qq);
+          Dm += al;
+          Nm = fma(al, d, Nm);
+        }
+        inc[q][c] = sp[q] * (Np * rcp(Dp)) - sm[q] * (Nm * rcp(Dm));
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      T R[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v)
+        R[v] = W0[v] + (Rm[v][0] * inc[q][0] + Rm[v][1] * inc[q][1] + Rm[v][2] * inc[q][2] +
+                        Rm[v][3] * inc[q][3]);
+      store_state<T, V>(fs + (2 * k + q) * V, R);
+    }
+  }
+}
+
 // Point values of the quadratic P^2 (eq. (polynomial-eta)): the linear scheme.
 template <typename T, int NF, int V>
 __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double* lds, int len,
@@ -293,11 +443,14 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double
 // Persistent reconstruction over the tiles of one cell type.  Dynamic LDS:
 // the staged cell averages (FP64, padded to 16 bytes), then the tile's face
 // states, written out in one coalesced block per tile.
-template <typename T, int NF, int V, bool LINEAR>
+// KIND: 0 WENO on the conserved variables, 1 the linear scheme, 2 WENO on
+// the characteristic variables (Euler).
+template <typename T, int NF, int V, int KIND>
 // Occupancy measured on gfx950: the quadrilateral kernel runs fastest with
-// the whole register file (1 wave per SIMD), the triangle kernel with 2.
-__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 ? 2 : 1) void k_recon(
-    const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta) {
+// the whole register file (1 wave per SIMD), the triangle kernel with 2
+// (the characteristic variant needs more registers than 2 waves allow).
+__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 && KIND != 2 ? 2 : 1) void k_recon(
+    const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
   extern __shared__ double lds[];
   const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
   const int t0 = NF == 4 ? 0 : m.n_tq, nt = NF == 4 ? m.n_tq : m.n_tt;
@@ -312,14 +465,28 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 ? 2 : 1) void
     const bool act = (int)threadIdx.x < tl.count;
     const int64_t r = tl.row0 + threadIdx.x;
     WenoIn<T, NF> in;
-    if (!LINEAR && kPrefetch<NF> && act) weno_load<T, NF>(td, r, in);
+    if (KIND != 1 && kPrefetch<NF> && act) weno_load<T, NF>(td, r, in);
     const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);
     if (act) {
       T* fs = fs_lds + threadIdx.x * STRIDE;
-      if (LINEAR)
+      if constexpr (KIND == 1) {
         linear_cell<T, NF, V>(td, r, lds, len, fs);
-      else
+      } else if constexpr (KIND == 2 && V == 4) {
+        // the cell's outward normals: the stored canonical normal, reversed
+        // where the neighbour is the left cell of the face
+        const int64_t i = tl.first + threadIdx.x;
+        T nrm[NF][2];
+#pragma unroll
+        for (int k = 0; k < NF; ++k) {
+          const int32_t pk = m.fnb[k * m.N + i];
+          const T s = (pk < 0 || (pk & 1)) ? T(1) : T(-1);
+          nrm[k][0] = s * m.fnrm[(k * 2 + 0) * m.N + i];
+          nrm[k][1] = s * m.fnrm[(k * 2 + 1) * m.N + i];
+        }
+        weno_cell_char<T, NF>(td, r, in, lds, len, nrm, fs, eps, theta, gam);
+      } else {
         weno_cell<T, NF, V>(td, r, in, lds, len, fs, eps, theta);
+      }
     }
     __syncthreads();
     // the tile's face states are contiguous in FS: copy them in 16-byte units
@@ -584,10 +751,10 @@ size_t lds_limit() {
 }
 
 template <typename T>
-hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule& sch, int nvar,
-                        const double* W, T* FS, hipStream_t st) {
-  const bool lin = s.mode == 1;
-  const T eps = (T)s.eps, th = (T)s.theta;
+hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& p,
+                        const Schedule& sch, int nvar, const double* W, T* FS, hipStream_t st) {
+  const int kind = s.mode == 1 ? 1 : (s.vars == 1 && nvar == 4 ? 2 : 0);
+  const T eps = (T)s.eps, th = (T)s.theta, gam = (T)p.gamma;
   auto one = [&](int ntiles, int maxlen, int want, auto nf_tag) -> hipError_t {
     constexpr int NF = decltype(nf_tag)::value;
     if (ntiles <= 0) return hipSuccess;
@@ -595,16 +762,18 @@ hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule&
     const size_t shm = (size_t)((maxlen * nvar + 1) & ~1) * sizeof(double) +
                        (size_t)kTileCells * (8 * nvar * sizeof(T) + 16);
     if (shm > lds_limit()) return hipErrorInvalidConfiguration;
-    if (lin) {
+    if (kind == 1) {
       if (nvar == 4)
-        k_recon<T, NF, 4, true><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
+        k_recon<T, NF, 4, 1><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
       else
-        k_recon<T, NF, 1, true><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
+        k_recon<T, NF, 1, 1><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
+    } else if (kind == 2) {
+      k_recon<T, NF, 4, 2><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
     } else {
       if (nvar == 4)
-        k_recon<T, NF, 4, false><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
+        k_recon<T, NF, 4, 0><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
       else
-        k_recon<T, NF, 1, false><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th);
+        k_recon<T, NF, 1, 0><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
     }
     return hipGetLastError();
   };
@@ -663,10 +832,11 @@ hipError_t launch_advance(int n_inst, double* t, const double* dt, hipStream_t s
   return hipGetLastError();
 }
 
-template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, const Schedule&,
-                                         int, const double*, double*, hipStream_t);
-template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, const Schedule&,
-                                        int, const double*, float*, hipStream_t);
+template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, const PhysDev&,
+                                         const Schedule&, int, const double*, double*,
+                                         hipStream_t);
+template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, const PhysDev&,
+                                        const Schedule&, int, const double*, float*, hipStream_t);
 template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, const Schedule&,
                                         int, int, const double*, const double*, const double*,
                                         double*, const double*, int*, hipStream_t);

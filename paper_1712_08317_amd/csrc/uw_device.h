@@ -56,6 +56,7 @@ struct PhysDev {
 struct SchemeDev {
   double eps, theta;
   int mode;       // 0 WENO, 1 linear
+  int vars;       // 0 conserved, 1 characteristic variables (Euler)
 };
 
 // Launch shape: number of persistent blocks of each kernel (0 = one block
@@ -66,8 +67,8 @@ struct Schedule {
 
 // Face states at the Gauss points: FS[(i*8 + g)*V + v].
 template <typename T>
-hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const Schedule& sch, int nvar,
-                        const double* W, T* FS, hipStream_t st);
+hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& p,
+                        const Schedule& sch, int nvar, const double* W, T* FS, hipStream_t st);
 
 // Flux, residual gather and RK stage.  mode 0: W_out = L(W_in); mode 1..3:
 // the three stages of the TVD Runge-Kutta scheme from W_in, Wn and dt[inst].

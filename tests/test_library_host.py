@@ -120,6 +120,9 @@ def test_call_order_and_arguments(uw):
     with pytest.raises(uw.UwError) as e:
         M.precompute(uw.make_scheme(eps=-1.0))
     assert e.value.status == uw.UW_EINVAL
+    with pytest.raises(uw.UwError) as e:
+        M.precompute(uw.make_scheme(variables=5))
+    assert e.value.status == uw.UW_EINVAL
     M.precompute()
     with pytest.raises(uw.UwError) as e:        # host-only mesh
         M.residual(ph, W, W, stream=0)
