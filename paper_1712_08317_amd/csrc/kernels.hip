@@ -297,8 +297,8 @@ __device__ inline void roe_eigen(const T* WA, const T* WB, T nx, T ny, T gam, T 
 // points of the face are projected back.
 template <typename T, int NF>
 __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
-                                      const double* lds, int len, const T (&nrm)[NF][2], T* fs,
-                                      T eps, T theta, T gam) {
+                                      const double* lds, int len, const MeshDev<T>& m,
+                                      int64_t i, T* fs, T eps, T theta, T gam) {
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, V = 4;
   const int64_t n = td.Nt;
@@ -323,11 +323,19 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
     // Roe mean of the cell and the neighbour across face k (slot k + 1)
     T Rm[4][4], Lm[4][4], Wk[V];
     {
-      const int l = li(k + 1);
+      // face neighbour: slot k + 1 (read again per face: indexing the
+      // prefetched slot list with the loop counter would place it in
+      // private memory)
+      const int l = td.lidx[(k + 1) * n + r];
 #pragma unroll
       for (int v = 0; v < V; ++v) Wk[v] = (T)lds[v * len + l];
     }
-    roe_eigen<T>(W0, Wk, nrm[k][0], nrm[k][1], gam, Rm, Lm);
+    // the cell's outward normal: the stored canonical normal, reversed where
+    // the neighbour is the left cell of the face
+    const int32_t pk = m.fnb[k * m.N + i];
+    const T sg = (pk < 0 || (pk & 1)) ? T(1) : T(-1);
+    roe_eigen<T>(W0, Wk, sg * m.fnrm[(k * 2 + 0) * m.N + i], sg * m.fnrm[(k * 2 + 1) * m.N + i],
+                 gam, Rm, Lm);
     // split linear weights of the face's two Gauss points
     T gp[2][M], gm[2][M], sp[2], sm[2], ox[2], oy[2];
 #pragma unroll
@@ -446,10 +454,12 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double
 // KIND: 0 WENO on the conserved variables, 1 the linear scheme, 2 WENO on
 // the characteristic variables (Euler).
 template <typename T, int NF, int V, int KIND>
-// Occupancy measured on gfx950: the quadrilateral kernel runs fastest with
-// the whole register file (1 wave per SIMD), the triangle kernel with 2
-// (the characteristic variant needs more registers than 2 waves allow).
-__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 && KIND != 2 ? 2 : 1) void k_recon(
+// Occupancy measured on gfx950 (FP32): the conserved-variable quadrilateral
+// kernel runs fastest with the whole register file (its candidate state
+// fits the 256 VGPRs of 2 waves per SIMD by itself), the triangle kernels
+// and the characteristic quadrilateral kernel with 2 waves per SIMD forced
+// (the latter then spills one 4-byte value and runs 39% faster than at 1).
+__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && (NF == 3 || KIND == 2) ? 2 : 1) void k_recon(
     const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
   extern __shared__ double lds[];
   const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
@@ -472,18 +482,8 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && NF == 3 && KIND != 2 
       if constexpr (KIND == 1) {
         linear_cell<T, NF, V>(td, r, lds, len, fs);
       } else if constexpr (KIND == 2 && V == 4) {
-        // the cell's outward normals: the stored canonical normal, reversed
-        // where the neighbour is the left cell of the face
-        const int64_t i = tl.first + threadIdx.x;
-        T nrm[NF][2];
-#pragma unroll
-        for (int k = 0; k < NF; ++k) {
-          const int32_t pk = m.fnb[k * m.N + i];
-          const T s = (pk < 0 || (pk & 1)) ? T(1) : T(-1);
-          nrm[k][0] = s * m.fnrm[(k * 2 + 0) * m.N + i];
-          nrm[k][1] = s * m.fnrm[(k * 2 + 1) * m.N + i];
-        }
-        weno_cell_char<T, NF>(td, r, in, lds, len, nrm, fs, eps, theta, gam);
+        weno_cell_char<T, NF>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta,
+                              gam);
       } else {
         weno_cell<T, NF, V>(td, r, in, lds, len, fs, eps, theta);
       }
