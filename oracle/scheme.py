@@ -37,8 +37,13 @@ Readings:
 * every face flux is evaluated in a canonical orientation: the left state is
   the cell with the lower original id, the normal is that cell's outer
   normal, and both cells use the same value with opposite signs;
-* a transmissive boundary face takes the interior reconstructed state on
-  both sides;
+* boundary faces (the paper names the conditions of its tests but does not
+  define them): the state outside a face is the inner reconstructed state
+  (transmissive, "non-reflecting"), the inner state with its normal
+  momentum reversed (reflective, a slip wall), or a prescribed state
+  (inflow).  The same outside state, formed from the cell average, is the
+  value of the mirrored ghost cell in the face neighbour's stencil slot;
+  for scalar advection a wall is treated as transmissive;
 * time step: dt = CFL min_i 2|Omega_i| / sum_p |l_p| (|u_i . n_p| + c_i), from
   cell averages (c = 0 and u = a for scalar advection), clamped to t_end - t.
   The paper instead fixes dt = 0.3 h for its accuracy runs.
@@ -62,6 +67,44 @@ class Physics:
     @property
     def nvar(self) -> int:
         return 4 if self.equation == "euler" else 1
+
+
+# --------------------------------------------------------------------------
+# boundary faces
+# --------------------------------------------------------------------------
+
+BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 1, 2, 3
+
+
+def face_kind(mesh, cells, k):
+    """Boundary kind of face k of the given cells (meaningful where the face
+    is unmatched): the per-face kind, else the mesh's default."""
+    cells = np.asarray(cells)
+    kind = np.full(cells.shape, BC_TRANSMISSIVE, dtype=np.int64)
+    if getattr(mesh, "face_bc", None) is not None:
+        fk = np.asarray(mesh.face_bc)[cells, k].astype(np.int64)
+        kind = np.where(fk > 0, fk, kind)
+    return kind
+
+
+def ghost_state(Wv, kind, nx, ny, inflow=None):
+    """State outside a boundary face with outward unit normal (nx, ny):
+    transmissive - the inner state; reflective - the inner state with its
+    normal momentum reversed; inflow s (kind 3 + s) - prescribed state s.
+    Wv: [V, ...]; kind, nx, ny broadcast against Wv[0]."""
+    Wv = np.asarray(Wv, dtype=np.float64)
+    out = Wv.copy()
+    kind = np.broadcast_to(kind, Wv.shape[1:])
+    if Wv.shape[0] == 4:
+        mn = Wv[1] * nx + Wv[2] * ny
+        refl = kind == BC_REFLECTIVE
+        out[1] = np.where(refl, Wv[1] - 2.0 * mn * nx, out[1])
+        out[2] = np.where(refl, Wv[2] - 2.0 * mn * ny, out[2])
+    if inflow is not None and (kind >= BC_INFLOW).any():
+        st = np.asarray(inflow, dtype=np.float64)[np.maximum(kind - BC_INFLOW, 0)]  # [..., 4]
+        for v in range(Wv.shape[0]):
+            out[v] = np.where(kind >= BC_INFLOW, st[..., v], out[v])
+    return out
 
 
 # --------------------------------------------------------------------------
@@ -133,12 +176,22 @@ def _nonlinear_combination(gp, sp, gm, sm, beta, d, eps):
     return out                                          # [F,m,G]
 
 
-def _weno_group(g, W, scheme, rows, gamma=1.4):
+def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None):
     st = g.st
     cells = st.cells[rows]
     rc = st.runtime_cell[rows]                          # [m,S]
     W0 = W[:, cells]                                    # [V,m]
     dW = W[:, rc] - W0[:, :, None]                      # [V,m,S]
+    # ghost face neighbours carry the outside state of their face
+    gh = st.ghost[rows]
+    for k in range(st.spec.n):
+        b = gh[:, k + 1] >= 0
+        if mesh is None or not b.any():
+            continue
+        nrm = g.normal[rows][:, k]
+        ghost = ghost_state(W0, face_kind(mesh, cells, k), nrm[:, 0], nrm[:, 1],
+                            getattr(mesh, "inflow", None))
+        dW[:, :, k + 1] = np.where(b[None], ghost - W0, dW[:, :, k + 1])
     Y = g.Y[rows]                                       # [m,M,2,2]
     off = g.gp_off[rows]                                # [m,G,2]
     M = st.spec.M
@@ -165,8 +218,8 @@ def _weno_group(g, W, scheme, rows, gamma=1.4):
         # projection of each Gauss point: Roe mean of the cell and the
         # neighbour across the point's face, with that face's normal
         face = np.arange(G) // 2
-        nbr = rc[:, 1 + face]                           # [m,G]
-        u, v, H, c = roe_average(W0[:, :, None], W[:, nbr], gamma)
+        Wnb = W0[:, :, None] + dW[:, :, 1 + face]       # [V,m,G] face neighbour or ghost
+        u, v, H, c = roe_average(W0[:, :, None], Wnb, gamma)
         nrm = g.normal[rows][:, face]                   # [m,G,2]
         Rm, Li, _ = eigenvectors(u, v, H, c, nrm[..., 0], nrm[..., 1], gamma)   # [m,G,4,4]
         dc = np.einsum("mgcv,vmgj->cmgj", Li, d)
@@ -197,7 +250,7 @@ def reconstruct_face_states(tables: Tables, W, cells=None, gamma=1.4):
         rows = (tables.loc[mine] & 0xFFFFFFFF).astype(np.int64)
         step = 8192
         for i in range(0, rows.size, step):
-            R = _weno_group(g, W, tables.scheme, rows[i:i + step], gamma)
+            R = _weno_group(g, W, tables.scheme, rows[i:i + step], gamma, tables.mesh)
             for c, r in zip(mine[i:i + step], np.moveaxis(R, 1, 0)):
                 out[int(c)] = r
     return out
@@ -290,8 +343,12 @@ def residual(tables: Tables, W, physics: Physics, cells=None):
             if c < 0:
                 nx, ny = gi.normal[ri, k]
                 ln = gi.length[ri, k]
-                F0 = _face_flux(physics, Ri[:, 2 * k], Ri[:, 2 * k], nx, ny)
-                F1 = _face_flux(physics, Ri[:, 2 * k + 1], Ri[:, 2 * k + 1], nx, ny)
+                kind = face_kind(tables.mesh, [int(i)], k)[0]
+                inflow = getattr(tables.mesh, "inflow", None)
+                G0 = ghost_state(Ri[:, 2 * k], kind, nx, ny, inflow)
+                G1 = ghost_state(Ri[:, 2 * k + 1], kind, nx, ny, inflow)
+                F0 = _face_flux(physics, Ri[:, 2 * k], G0, nx, ny)
+                F1 = _face_flux(physics, Ri[:, 2 * k + 1], G1, nx, ny)
                 acc += ln * 0.5 * (F0 + F1)
                 continue
             kp = int(conn.nbr_face[i, k])
@@ -330,7 +387,7 @@ def residual_vectorized(tables: Tables, W, physics: Physics):
         for i in range(0, cells.size, step):
             rows = np.arange(i, min(cells.size, i + step))
             R[:, cells[rows], :2 * nf_value] = _weno_group(g, W, tables.scheme, rows,
-                                                           physics.gamma)
+                                                           physics.gamma, tables.mesh)
         normal[cells] = g.normal
         length[cells] = g.length
         area[cells] = g.area
@@ -348,10 +405,15 @@ def residual_vectorized(tables: Tables, W, physics: Physics):
         # unused face slots (k >= n) take a valid state; their flux is discarded
         Ri0 = np.where(valid[None], R[:, ids, 2 * k], R[:, ids, 0])
         Ri1 = np.where(valid[None], R[:, ids, 2 * k + 1], R[:, ids, 0])
-        Rc0 = np.where(inn[None], R[:, cc, 2 * kk + 1], Ri0)   # neighbour value at my point 0
-        Rc1 = np.where(inn[None], R[:, cc, 2 * kk], Ri1)
         nL = np.where((left | bnd)[:, None], normal[:, k], normal[cc, kk])
         nL = np.where(valid[:, None], nL, 1.0 / np.sqrt(2.0))
+        # outside of a boundary face: its ghost state
+        kind = face_kind(tables.mesh, ids, k)
+        inflow = getattr(tables.mesh, "inflow", None)
+        G0 = ghost_state(Ri0, kind, nL[:, 0], nL[:, 1], inflow)
+        G1 = ghost_state(Ri1, kind, nL[:, 0], nL[:, 1], inflow)
+        Rc0 = np.where(inn[None], R[:, cc, 2 * kk + 1], G0)    # neighbour value at my point 0
+        Rc1 = np.where(inn[None], R[:, cc, 2 * kk], G1)
         lL = np.where(left | bnd, length[:, k], length[cc, kk])
         WL0 = np.where((left | bnd)[None], Ri0, Rc0)
         WR0 = np.where((left | bnd)[None], Rc0, Ri0)

@@ -47,6 +47,10 @@ class Mesh:
     bc: str                      # "periodic" or "transmissive"
     h: float                     # nominal cell size
     name: str = ""
+    # boundary kind of each unmatched face [n_cells, 4] (BC_* below; 0 = bc),
+    # and the prescribed states that BC_INFLOW + s refers to [n_states, 4]
+    face_bc: np.ndarray | None = None
+    inflow: np.ndarray | None = None
 
     @property
     def n_cells(self) -> int:
@@ -58,6 +62,10 @@ class Mesh:
 
     def n_faces_of(self) -> np.ndarray:
         return np.where(self.cell_nodes[:, 3] < 0, 3, 4).astype(np.int32)
+
+
+# boundary kinds of unmatched faces (input description only)
+BC_DEFAULT, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
 
 
 # --------------------------------------------------------------------------
