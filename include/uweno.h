@@ -43,7 +43,7 @@ typedef enum {
   UW_ENONFINITE = 6   /* device flagged NaN/Inf or rho <= 0 / p <= 0             */
 } uw_status;
 
-enum { UW_BC_PERIODIC = 0, UW_BC_TRANSMISSIVE = 1 };
+enum { UW_BC_PERIODIC = 0, UW_BC_TRANSMISSIVE = 1, UW_BC_REFLECTIVE = 2, UW_BC_INFLOW = 3 };
 enum { UW_WENO = 0, UW_LINEAR = 1 };
 enum { UW_CONSERVED = 0, UW_CHARACTERISTIC = 1 };
 enum { UW_D_PER_GP = 0, UW_D_PER_CELL = 1 };
@@ -62,7 +62,19 @@ typedef struct uw_batch uw_batch;
  *             means every node is its own id.
  * bc          what an unmatched face is: UW_BC_TRANSMISSIVE (a mirrored ghost
  *             cell carrying the interior value), or UW_BC_PERIODIC (no
- *             unmatched face allowed). */
+ *             unmatched face allowed).
+ * face_bc     [n_cells][4] per-face kind of the unmatched faces, NULL = `bc`
+ *             for all; entries of matched faces are ignored.  0 = `bc`,
+ *             UW_BC_TRANSMISSIVE, UW_BC_REFLECTIVE (slip wall: the ghost and
+ *             the outside state of the face flux are the inner state with its
+ *             normal momentum reversed; transmissive for scalar advection),
+ *             UW_BC_INFLOW + s (prescribed conserved state s of inflow_W).
+ *             The paper's tests name non-reflecting, reflective and
+ *             prescribed-state boundaries (Sec. 4) without defining them.
+ * n_inflow, inflow_W  number and values [n_inflow][4] (rho, rho u, rho v,
+ *             rho E; advection uses the first) of the prescribed states.
+ * Errors: an unmatched face whose kind is UW_BC_PERIODIC gives UW_EMESH; a
+ * kind outside the list or an inflow index >= n_inflow gives UW_EINVAL. */
 typedef struct {
   int64_t n_nodes;
   const double* node_xy;
@@ -70,6 +82,9 @@ typedef struct {
   const int32_t* cell_nodes;
   const int32_t* node_id;
   int32_t bc;
+  const int32_t* face_bc;
+  int32_t n_inflow;
+  const double* inflow_W;
 } uw_mesh_desc;
 
 /* Scheme constants (paper Sec. 3): zeta of eq. (quadratic-2) (1e-14), theta

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("UWENO_LIB", os.path.join(HERE, "libuweno.so"))
 
 UW_OK, UW_EINVAL, UW_EMESH, UW_ESTATE, UW_ENOMEM, UW_EDEVICE, UW_ENONFINITE = range(7)
-UW_BC_PERIODIC, UW_BC_TRANSMISSIVE = 0, 1
+UW_BC_PERIODIC, UW_BC_TRANSMISSIVE, UW_BC_REFLECTIVE, UW_BC_INFLOW = 0, 1, 2, 3
 UW_WENO, UW_LINEAR = 0, 1
 UW_CONSERVED, UW_CHARACTERISTIC = 0, 1
 UW_D_PER_GP, UW_D_PER_CELL = 0, 1
@@ -37,7 +37,9 @@ class UwError(RuntimeError):
 class MeshDesc(ctypes.Structure):
     _fields_ = [("n_nodes", ctypes.c_int64), ("node_xy", ctypes.c_void_p),
                 ("n_cells", ctypes.c_int64), ("cell_nodes", ctypes.c_void_p),
-                ("node_id", ctypes.c_void_p), ("bc", ctypes.c_int32)]
+                ("node_id", ctypes.c_void_p), ("bc", ctypes.c_int32),
+                ("face_bc", ctypes.c_void_p), ("n_inflow", ctypes.c_int32),
+                ("inflow_W", ctypes.c_void_p)]
 
 
 class SchemeC(ctypes.Structure):
@@ -137,13 +139,19 @@ def make_physics(equation=UW_EULER, ax=1.0, ay=1.0, gamma=1.4, precision=UW_FP64
 class Mesh:
     """A mesh uploaded to the library (internal Hilbert numbering)."""
 
-    def __init__(self, node_xy, cell_nodes, node_id=None, bc=UW_BC_PERIODIC, device=0):
+    def __init__(self, node_xy, cell_nodes, node_id=None, bc=UW_BC_PERIODIC, device=0,
+                 face_bc=None, inflow=None):
         self._xy = np.ascontiguousarray(node_xy, dtype=np.float64)
         self._cn = np.ascontiguousarray(cell_nodes, dtype=np.int32)
         self._nid = None if node_id is None else np.ascontiguousarray(node_id, dtype=np.int32)
+        self._fbc = None if face_bc is None else np.ascontiguousarray(face_bc, dtype=np.int32)
+        self._inf = (None if inflow is None
+                     else np.ascontiguousarray(np.asarray(inflow, dtype=np.float64).reshape(-1, 4)))
         desc = MeshDesc(self._xy.shape[0], self._xy.ctypes.data, self._cn.shape[0],
                         self._cn.ctypes.data, None if self._nid is None else self._nid.ctypes.data,
-                        bc)
+                        bc, None if self._fbc is None else self._fbc.ctypes.data,
+                        0 if self._inf is None else self._inf.shape[0],
+                        None if self._inf is None else self._inf.ctypes.data)
         h = ctypes.c_void_p()
         _check(LIB.uw_mesh_upload(ctypes.byref(desc), device, ctypes.byref(h)))
         self.handle = h
@@ -162,7 +170,8 @@ class Mesh:
     @classmethod
     def from_workload(cls, mesh, device=0):
         bc = UW_BC_PERIODIC if mesh.bc == "periodic" else UW_BC_TRANSMISSIVE
-        return cls(mesh.node_xy, mesh.cell_nodes, mesh.node_id, bc, device)
+        return cls(mesh.node_xy, mesh.cell_nodes, mesh.node_id, bc, device,
+                   getattr(mesh, "face_bc", None), getattr(mesh, "inflow", None))
 
     def __del__(self):
         h = getattr(self, "handle", None)

@@ -136,6 +136,7 @@ struct Staged {
   int32_t n_inst = 0, n_tq = 0, n_tt = 0, max_len_q = 0, max_len_t = 0;
   std::vector<uw::Tile> tiles;
   std::vector<int32_t> tile_off, tile_ids, inst_tiles, fnb;
+  std::vector<double> inflow;   // [n_states][4] prescribed states of all instances
   int64_t rows_q = 0, rows_t = 0;
   std::vector<uint16_t> q_lidx, t_lidx;
   std::vector<double> q_Y, q_off, q_gam, q_eta, t_Y, t_off, t_gam, t_eta, fgeo;
@@ -221,16 +222,19 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
       cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.eta; },
                R, ro, q ? S.q_eta : S.t_eta);
   }
-  // face tables
+  // face tables; prescribed states of all instances in one table
   S.fnb.assign(4 * S.N, -1);
   S.fgeo.assign(12 * S.N, 0.0);
   for (int k = 0; k < n; ++k) {
     const int64_t Nk = ms[k]->N;
+    const int32_t soff = (int32_t)(S.inflow.size() / 4);
+    S.inflow.insert(S.inflow.end(), ms[k]->inflow.begin(), ms[k]->inflow.end());
     for (int c = 0; c < 4; ++c)
       for (int64_t i = 0; i < Nk; ++i) {
         const int32_t p = ts[k]->fnb[c * Nk + i];
         S.fnb[c * S.N + off[k] + i] =
-            p < 0 ? p : (int32_t)((((int64_t)(p >> 3) + off[k]) << 3) | (p & 7));
+            p <= -3 ? p - soff
+                    : p < 0 ? p : (int32_t)((((int64_t)(p >> 3) + off[k]) << 3) | (p & 7));
       }
     for (int c = 0; c < 12; ++c)
       std::copy(ts[k]->fgeo.begin() + c * Nk, ts[k]->fgeo.begin() + (c + 1) * Nk,
@@ -242,11 +246,12 @@ template <class T>
 struct DevTables {
   bool ready = false;
   DevBuf tiles, tile_off, tile_ids, inst_tiles, q_li, q_Y, q_off, q_gam, q_eta, t_li, t_Y, t_off,
-      t_gam, t_eta, fnb, fnrm, fcoef;
+      t_gam, t_eta, fnb, fnrm, fcoef, inflow;
   uw::MeshDev<T> view;
   void reset() {
     for (DevBuf* b : {&tiles, &tile_off, &tile_ids, &inst_tiles, &q_li, &q_Y, &q_off, &q_gam,
-                      &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fnrm, &fcoef})
+                      &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fnrm, &fcoef,
+                      &inflow})
       b->release();
     view = uw::MeshDev<T>();
     ready = false;
@@ -329,6 +334,7 @@ uw_status ensure_tables(Engine& E) {
   up(d.t_gam, convert<T>(S.t_gam));
   up(d.t_eta, convert<T>(S.t_eta));
   up(d.fnb, S.fnb);
+  if (!S.inflow.empty()) up(d.inflow, S.inflow);
   {
     std::vector<T> nrm;
     std::vector<double> coef;
@@ -362,6 +368,7 @@ uw_status ensure_tables(Engine& E) {
   v.tri.gam = d.t_gam.template as<T>();
   v.tri.eta = d.t_eta.template as<T>();
   v.fnb = d.fnb.template as<int32_t>();
+  v.inflow = S.inflow.empty() ? nullptr : d.inflow.template as<double>();
   v.fnrm = d.fnrm.template as<T>();
   v.fcoef = d.fcoef.template as<double>();
   d.ready = true;
@@ -561,13 +568,16 @@ uw_status uw_mesh_upload(const uw_mesh_desc* desc, int device, uw_mesh** out) {
   if (desc->bc != UW_BC_PERIODIC && desc->bc != UW_BC_TRANSMISSIVE)
     return fail(UW_EINVAL, "bc must be UW_BC_PERIODIC or UW_BC_TRANSMISSIVE");
   if (desc->n_cells > (int64_t(1) << 28)) return fail(UW_EINVAL, "at most 2^28 cells");
+  if (desc->n_inflow < 0 || desc->n_inflow > (1 << 20) || (desc->n_inflow > 0 && !desc->inflow_W))
+    return fail(UW_EINVAL, "n_inflow must be in [0, 2^20] with inflow_W given");
   uw_mesh* m = new (std::nothrow) uw_mesh();
   if (!m) return fail(UW_ENOMEM, "host allocation");
   m->eng.device = device;
   uw::Error err;
   try {
     if (!uw::build_mesh(desc->n_nodes, desc->node_xy, desc->n_cells, desc->cell_nodes,
-                        desc->node_id, desc->bc, m->host, err)) {
+                        desc->node_id, desc->bc, desc->face_bc, desc->n_inflow, desc->inflow_W,
+                        m->host, err)) {
       delete m;
       return fail((uw_status)err.code, err.msg);
     }

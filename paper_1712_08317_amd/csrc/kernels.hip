@@ -116,6 +116,47 @@ __device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const 
   return len;
 }
 
+// State outside a boundary face of kind -pk (pk < 0) with outward unit
+// normal (nx, ny), from the inner state w: -1 transmissive (w itself), -2
+// slip wall (w with its normal momentum reversed; transmissive for a scalar),
+// -3 - s prescribed state s.
+template <typename U, int V>
+__device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny,
+                                     const double* __restrict__ inflow, U* g) {
+#pragma unroll
+  for (int v = 0; v < V; ++v) g[v] = w[v];
+  if (pk == -2) {
+    if constexpr (V == 4) {
+      const U mn = w[1] * nx + w[2] * ny;
+      g[1] = w[1] - U(2) * mn * nx;
+      g[2] = w[2] - U(2) * mn * ny;
+    }
+  } else if (pk <= -3) {
+    const double* st = inflow + 4 * (-3 - pk);
+#pragma unroll
+    for (int v = 0; v < V; ++v) g[v] = (U)st[v];
+  }
+}
+
+// Ghost face neighbours of a wall or inflow face carry that face's outside
+// state (a transmissive ghost reads the cell itself, as staged): replace
+// the difference of slot k + 1, the neighbour across face k.
+template <typename T, int NF, int V>
+__device__ inline void ghost_differences(const MeshDev<T>& m, int64_t i, const double* w0,
+                                         T (&dW)[Layout<NF>::S - 1][V]) {
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int32_t pk = m.fnb[k * m.N + i];
+    if (pk <= -2) {
+      double g[V];
+      outside_state<double, V>(pk, w0, (double)m.fnrm[(k * 2 + 0) * m.N + i],
+                               (double)m.fnrm[(k * 2 + 1) * m.N + i], m.inflow, g);
+#pragma unroll
+      for (int v = 0; v < V; ++v) dW[k][v] = (T)(g[v] - w0[v]);
+    }
+  }
+}
+
 // Per-cell inputs of the WENO reconstruction that do not depend on the
 // state.  Latency hiding (measured on gfx950): the triangle kernel reads them
 // before the tile's staging barrier, so that their latency overlaps the
@@ -147,7 +188,8 @@ __device__ inline void weno_load(const TypeDev<T>& td, int64_t r, WenoIn<T, NF>&
 // WENO point values of one cell at its 2n Gauss points (paper Sec. 3.4).
 template <typename T, int NF, int V>
 __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
-                                 const double* lds, int len, T* fs, T eps, T theta) {
+                                 const double* lds, int len, const MeshDev<T>& m, int64_t i,
+                                 T* fs, T eps, T theta) {
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, G = 2 * NF;
   const int64_t n = td.Nt;
@@ -174,6 +216,7 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
 #pragma unroll
     for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
+  ghost_differences<T, NF, V>(m, i, w0, dW);
   // candidate gradients g_j = Y_j (dW_a, dW_b) and indicators beta_j = |g_j|^2
   T gx[M][V], gy[M][V], be[M][V], bpe[M][V];
 #pragma unroll
@@ -318,11 +361,23 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
 #pragma unroll
     for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
+  ghost_differences<T, NF, V>(m, i, w0, dW);
 #pragma unroll 1
   for (int k = 0; k < NF; ++k) {
     // Roe mean of the cell and the neighbour across face k (slot k + 1)
     T Rm[4][4], Lm[4][4], Wk[V];
-    {
+    // the cell's outward normal: the stored canonical normal, reversed where
+    // the neighbour is the left cell of the face
+    const int32_t pk = m.fnb[k * m.N + i];
+    const T sg = (pk < 0 || (pk & 1)) ? T(1) : T(-1);
+    const T nxk = sg * m.fnrm[(k * 2 + 0) * m.N + i], nyk = sg * m.fnrm[(k * 2 + 1) * m.N + i];
+    if (pk <= -2) {
+      // a wall or inflow face: its outside state is the ghost neighbour
+      double g[V];
+      outside_state<double, V>(pk, w0, (double)nxk, (double)nyk, m.inflow, g);
+#pragma unroll
+      for (int v = 0; v < V; ++v) Wk[v] = (T)g[v];
+    } else {
       // face neighbour: slot k + 1 (read again per face: indexing the
       // prefetched slot list with the loop counter would place it in
       // private memory)
@@ -330,12 +385,7 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
 #pragma unroll
       for (int v = 0; v < V; ++v) Wk[v] = (T)lds[v * len + l];
     }
-    // the cell's outward normal: the stored canonical normal, reversed where
-    // the neighbour is the left cell of the face
-    const int32_t pk = m.fnb[k * m.N + i];
-    const T sg = (pk < 0 || (pk & 1)) ? T(1) : T(-1);
-    roe_eigen<T>(W0, Wk, sg * m.fnrm[(k * 2 + 0) * m.N + i], sg * m.fnrm[(k * 2 + 1) * m.N + i],
-                 gam, Rm, Lm);
+    roe_eigen<T>(W0, Wk, nxk, nyk, gam, Rm, Lm);
     // split linear weights of the face's two Gauss points
     T gp[2][M], gm[2][M], sp[2], sm[2], ox[2], oy[2];
 #pragma unroll
@@ -415,7 +465,7 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
 // Point values of the quadratic P^2 (eq. (polynomial-eta)): the linear scheme.
 template <typename T, int NF, int V>
 __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double* lds, int len,
-                                   T* fs) {
+                                   const MeshDev<T>& m, int64_t i, T* fs) {
   using L = Layout<NF>;
   constexpr int S = L::S, G = 2 * NF;
   const int64_t n = td.Nt;
@@ -430,6 +480,7 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double
 #pragma unroll
     for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
+  ghost_differences<T, NF, V>(m, i, w0, dW);
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
     T acc[V];
@@ -480,12 +531,12 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && (NF == 3 || KIND == 2
     if (act) {
       T* fs = fs_lds + threadIdx.x * STRIDE;
       if constexpr (KIND == 1) {
-        linear_cell<T, NF, V>(td, r, lds, len, fs);
+        linear_cell<T, NF, V>(td, r, lds, len, m, tl.first + threadIdx.x, fs);
       } else if constexpr (KIND == 2 && V == 4) {
         weno_cell_char<T, NF>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta,
                               gam);
       } else {
-        weno_cell<T, NF, V>(td, r, in, lds, len, fs, eps, theta);
+        weno_cell<T, NF, V>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta);
       }
     }
     __syncthreads();
@@ -596,11 +647,9 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
       load_state<T, V>(FS + (i * 8 + 2 * k + 1) * V, o1);
       bool left = true;
       if (pk < 0) {
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          t0[v] = o0[v];
-          t1[v] = o1[v];
-        }
+        // boundary face: the outside states (the stored normal is the cell's)
+        outside_state<T, V>(pk, o0, nx, ny, m.inflow, t0);
+        outside_state<T, V>(pk, o1, nx, ny, m.inflow, t1);
       } else {
         const int64_t c = pk >> 3;
         const int kp = (pk >> 1) & 3;
@@ -609,7 +658,14 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
         load_state<T, V>(FS + (c * 8 + 2 * kp + 1) * V, t0);
         load_state<T, V>(FS + (c * 8 + 2 * kp) * V, t1);
       }
-      if constexpr (V == 4) bad |= !(o0[0] > T(0)) || !(o1[0] > T(0));
+      if constexpr (V == 4) {
+        // an inadmissible reconstruction (the scheme is not positivity
+        // preserving): density or pressure not positive at a Gauss point
+        const T g1 = (T)p.gamma - T(1);
+        const T p0 = g1 * (o0[3] - T(0.5) * (o0[1] * o0[1] + o0[2] * o0[2]) / o0[0]);
+        const T p1 = g1 * (o1[3] - T(0.5) * (o1[1] * o1[1] + o1[2] * o1[2]) / o1[0]);
+        bad |= !(o0[0] > T(0)) || !(o1[0] > T(0)) || !(p0 > T(0)) || !(p1 > T(0));
+      }
       double F0[V], F1[V];
       if (left) {
         face_flux<T, V>(o0, t0, nx, ny, p, F0);

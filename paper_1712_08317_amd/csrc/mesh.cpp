@@ -103,12 +103,14 @@ static double shoelace(const double* xy, const int32_t* c, int nf) {
 }
 
 bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_t* cells,
-                const int32_t* node_id, int bc, HostMesh& m, Error& err) {
+                const int32_t* node_id, int bc, const int32_t* face_bc, int32_t n_inflow,
+                const double* inflow_W, HostMesh& m, Error& err) {
   const int threads = default_threads();
   m.n_nodes = n_nodes;
   m.N = n_cells;
   m.periodic = (bc == 0);
   m.xy.assign(xy, xy + 2 * n_nodes);
+  m.inflow.assign(inflow_W ? inflow_W : xy, inflow_W ? inflow_W + 4 * (int64_t)n_inflow : xy);
 
   // ---- validation
   std::vector<int32_t> nf0(n_cells);
@@ -177,6 +179,7 @@ bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_
   radix_sort(key, order);
   std::vector<int32_t> nbr0(4 * n_cells, -1);
   std::vector<int8_t> nface0(4 * n_cells, -1);
+  std::vector<int32_t> bkind0(4 * n_cells, 0);
   std::vector<double> shift0(8 * n_cells, 0.0);
   int64_t interior = 0;
   for (int64_t p = 0; p < H;) {
@@ -205,9 +208,22 @@ bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_
       shift0[8 * c2 + 2 * k2] = xy[2 * a2] - xy[2 * b1];
       shift0[8 * c2 + 2 * k2 + 1] = xy[2 * a2 + 1] - xy[2 * b1 + 1];
       ++interior;
-    } else if (m.periodic) {
-      err = {2, "unmatched face on a periodic mesh"};
-      return false;
+    } else {
+      // an unmatched face: its boundary kind
+      const int64_t h = order[p];
+      const int32_t c = he_cell[h];
+      const int k = he_k[h];
+      int kind = face_bc ? face_bc[4 * c + k] : 0;
+      if (kind == 0) kind = m.periodic ? 0 : 1;
+      if (kind == 0) {
+        err = {2, "unmatched face on a periodic mesh"};
+        return false;
+      }
+      if (kind < 0 || kind > 2 + n_inflow) {
+        err = {1, "face_bc: unknown kind or prescribed state index"};
+        return false;
+      }
+      bkind0[4 * c + k] = kind;
     }
     p = q;
   }
@@ -254,6 +270,7 @@ bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_
   m.nbr_face.assign(4 * n_cells, -1);
   m.shift.assign(8 * n_cells, 0.0);
   m.left.assign(4 * n_cells, 0);
+  m.bkind.assign(4 * n_cells, 0);
   parallel_for(n_cells, threads, [&](int64_t s, int64_t e) {
     for (int64_t i = s; i < e; ++i) {
       int64_t o = m.old_of_new[i];
@@ -270,6 +287,7 @@ bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_
             m.left[4 * i + k] = (o < nb) ? 1 : 0;
           } else {
             m.left[4 * i + k] = 1;
+            m.bkind[4 * i + k] = bkind0[4 * o + k];
           }
         }
       }

@@ -168,6 +168,8 @@ void finish_tables(const HostMesh& m, HostTables& t, const std::vector<double>& 
         }
         if (nb >= 0)
           t.fnb[k * N + i] = (nb << 3) | (m.nbr_face[4 * i + k] << 1) | (left ? 1 : 0);
+        else
+          t.fnb[k * N + i] = -m.bkind[4 * i + k];   // boundary: minus its kind
         const double coef = ln / (2.0 * t.area[i]);
         t.fgeo[(k * 3 + 0) * N + i] = nx;
         t.fgeo[(k * 3 + 1) * N + i] = ny;

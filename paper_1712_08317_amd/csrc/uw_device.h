@@ -43,7 +43,9 @@ struct MeshDev {
   int32_t max_len_q = 0, max_len_t = 0;
   const int32_t* inst_tiles = nullptr; // [2][n_inst + 1] quad / triangle tile ranges per instance
   TypeDev<T> quad, tri;
-  const int32_t* fnb = nullptr;     // [4][N] (nbr << 3) | (nbr_face << 1) | left, -1 boundary
+  const int32_t* fnb = nullptr;     // [4][N] (nbr << 3) | (nbr_face << 1) | left; boundary:
+                                    // -1 transmissive, -2 reflective, -3 - s prescribed state s
+  const double* inflow = nullptr;   // [n_states][4] prescribed states (conserved)
   const T* fnrm = nullptr;          // [4*2][N] canonical unit normal of each face
   const double* fcoef = nullptr;    // [4][N] |l| / (2 |Omega_i|), closed for the stored normals
 };

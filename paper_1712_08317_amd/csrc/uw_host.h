@@ -48,6 +48,10 @@ struct HostMesh {
   std::vector<int8_t> nbr_face;      // [N*4]
   std::vector<double> shift;         // [N*4*2]
   std::vector<uint8_t> left;         // [N*4] 1: this cell is the canonical left state
+  // boundary kind of each unmatched face: 1 transmissive, 2 reflective,
+  // 3 + s prescribed state s; 0 for matched and unused faces
+  std::vector<int32_t> bkind;        // [N*4]
+  std::vector<double> inflow;        // [n_inflow*4] prescribed conserved states
   // stencils
   std::vector<int32_t> st_cell;      // [N*13] slot cell (ghost: self; absent: -1)
   std::vector<double> st_shift;      // [N*13*2]
@@ -60,7 +64,8 @@ struct HostMesh {
 // Builds connectivity, renumbering and stencils.  Returns false and fills
 // err on an invalid mesh.
 bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_t* cells,
-                const int32_t* node_id, int bc, HostMesh& m, Error& err);
+                const int32_t* node_id, int bc, const int32_t* face_bc, int32_t n_inflow,
+                const double* inflow_W, HostMesh& m, Error& err);
 
 struct SchemeParams {
   double zeta = 1e-14, theta = 3.0, eps = 1e-3;
@@ -86,7 +91,7 @@ struct TypeTables {
 
 struct HostTables {
   TypeTables quad, tri;
-  std::vector<int32_t> fnb;     // [4][N] (nbr << 3) | (nbr_face << 1) | left; -1 boundary
+  std::vector<int32_t> fnb;     // [4][N] (nbr << 3) | (nbr_face << 1) | left; boundary: -kind
   std::vector<double> fgeo;     // [4*3][N] canonical normal nx, ny and |l|/(2|Omega_i|)
   std::vector<double> area;     // [N]
   // full per-cell copies for inspection (kept for small meshes only)

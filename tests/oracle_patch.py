@@ -95,8 +95,13 @@ def patch_mesh(mesh, inc: NodeIncidence, centre_cell: int, rings: int):
                 new_nodes[key] = j
                 node_xy.append(p)
             out[r, k] = j
+    # real boundary faces keep their kind; the faces the cut opens take
+    # whatever their row says, which cannot reach the centre cell
+    fbc = getattr(mesh, "face_bc", None)
     sub = wl.Mesh(node_xy=np.array(node_xy, dtype=np.float64), cell_nodes=out, node_id=None,
-                  period=(0.0, 0.0), bc="transmissive", h=mesh.h, name=f"patch{centre_cell}")
+                  period=(0.0, 0.0), bc="transmissive", h=mesh.h, name=f"patch{centre_cell}",
+                  face_bc=None if fbc is None else np.asarray(fbc)[cells],
+                  inflow=getattr(mesh, "inflow", None))
     return sub, cells
 
 

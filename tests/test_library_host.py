@@ -143,3 +143,27 @@ def test_diagnostics_report_optimisation(uw):
     assert d["max_abs_gamma_opt"] < 12 and d["resid_opt"] < 1e-9
     d0 = M.precompute(uw.make_scheme(optimize=False))
     assert d0["max_abs_gamma_opt"] == pytest.approx(d["max_abs_gamma_raw"], rel=1e-9)
+
+
+def test_boundary_kinds_are_validated(uw):
+    mesh = wl.box_mesh(wl.BC_REFLECTIVE, n=6)
+    M = uw.Mesh.from_workload(mesh, device=-1)
+    M.precompute()
+    bad = mesh.face_bc.copy()
+    bad[:] = 7                                   # inflow state 4 of none
+    with pytest.raises(uw.UwError) as e:
+        uw.Mesh(mesh.node_xy, mesh.cell_nodes, None, uw.UW_BC_TRANSMISSIVE, device=-1,
+                face_bc=bad)
+    assert e.value.status == uw.UW_EINVAL
+    # with the state given it is accepted
+    uw.Mesh(mesh.node_xy, mesh.cell_nodes, None, uw.UW_BC_TRANSMISSIVE, device=-1,
+            face_bc=np.full_like(bad, uw.UW_BC_INFLOW), inflow=np.ones((1, 4)))
+    # an unmatched face left periodic is not a mesh
+    per = mesh.face_bc.copy()
+    per[:] = 0
+    with pytest.raises(uw.UwError) as e:
+        uw.Mesh(mesh.node_xy, mesh.cell_nodes, None, uw.UW_BC_PERIODIC, device=-1, face_bc=per)
+    assert e.value.status == uw.UW_EMESH
+    # the stencils do not depend on the kinds
+    M2 = uw.Mesh(mesh.node_xy, mesh.cell_nodes, None, uw.UW_BC_TRANSMISSIVE, device=-1)
+    assert all(np.array_equal(a, b) for a, b in zip(M.export(), M2.export()))

@@ -375,6 +375,131 @@ WORKLOADS = {
 }
 
 
+# --------------------------------------------------------------------------
+# boundary kinds and the paper's other test problems (Sec. 4.2-4.4)
+# --------------------------------------------------------------------------
+
+def set_face_kinds(mesh: Mesh, kind_of) -> Mesh:
+    """Fill mesh.face_bc from ``kind_of(mx, my, nx, ny)`` evaluated at every
+    face's midpoint with its outward normal (the library and the oracle read
+    it only on unmatched faces)."""
+    cn = mesh.cell_nodes
+    nf = np.where(cn[:, 3] < 0, 3, 4)
+    kinds = np.zeros((mesh.n_cells, 4), np.int32)
+    for k in range(4):
+        valid = k < nf
+        a = mesh.node_xy[np.maximum(cn[:, k], 0)]
+        nxt = np.where(k + 1 < nf, (k + 1) % 4, 0)
+        b = mesh.node_xy[np.maximum(cn[np.arange(mesh.n_cells), nxt], 0)]
+        m = 0.5 * (a + b)
+        t = b - a
+        ln = np.maximum(np.hypot(t[:, 0], t[:, 1]), 1e-300)
+        kinds[:, k] = np.where(valid, kind_of(m[:, 0], m[:, 1], t[:, 1] / ln, -t[:, 0] / ln), 0)
+    mesh.face_bc = kinds
+    return mesh
+
+
+def box_mesh(kind: int, n: int = 12, jitter: float = 0.25, seed: int = 3,
+             inflow=None) -> Mesh:
+    """Open unit square, n x n squares in 3 x 3 blocks alternating between
+    quadrilaterals and split triangles, every boundary face of one kind."""
+    split = (np.add.outer(np.arange(n) // 3, np.arange(n) // 3) % 2).astype(bool)
+    mesh = grid_mesh(n, n, 1.0, 1.0, split, jitter, seed, False, name=f"box{kind}-{n}")
+    mesh.face_bc = np.full((mesh.n_cells, 4), kind, dtype=np.int32)
+    if inflow is not None:
+        mesh.inflow = np.asarray(inflow, dtype=np.float64).reshape(-1, 4)
+    return mesh
+
+
+def channel_mesh(nx: int = 20, ny: int = 10, split="tri", jitter: float = 0.2, seed: int = 9,
+                 inflow=None, lx: float = 2.0, ly: float = 1.0) -> Mesh:
+    """Channel [0,lx] x [0,ly]: slip walls top and bottom, the prescribed
+    state 0 entering on the left, an open right end."""
+    mesh = grid_mesh(nx, ny, lx, ly, split, jitter, seed, False, name=f"channel{nx}x{ny}")
+    tol = 1e-9 * max(lx, ly)
+
+    def kind_of(mx, my, nx_, ny_):
+        wall = (np.abs(my) < tol) | (np.abs(my - ly) < tol)
+        left = np.abs(mx) < tol
+        return np.where(wall, BC_REFLECTIVE, np.where(left, BC_INFLOW, BC_TRANSMISSIVE))
+    set_face_kinds(mesh, kind_of)
+    if inflow is not None:
+        mesh.inflow = np.asarray(inflow, dtype=np.float64).reshape(-1, 4)
+    return mesh
+
+
+def lax_state(mesh: Mesh, gamma=GAMMA) -> np.ndarray:
+    """Lax problem (Sec. 4.2): (0.445, 0.698, 3.528) for x < 0.5, else
+    (0.5, 0, 0.571), sampled at vertex averages."""
+    cx, cy = cell_centres(mesh)
+    left = cx < 0.5
+    rho = np.where(left, 0.445, 0.5)
+    u = np.where(left, 0.698, 0.0)
+    p = np.where(left, 3.528, 0.571)
+    return primitive_to_conserved(rho, u, np.zeros_like(u), p, gamma)
+
+
+def shu_osher(nx: int = 400, ny: int = 10, jitter: float = 0.3, seed: int = 11,
+              split="quad", gamma=GAMMA):
+    """Shu-Osher problem as the paper sets it (Sec. 4.2): [0,10] x [0,0.25],
+    (3.857134, 2.629369, 10.33333) for x <= 1, else (1 + 0.2 sin 5x, 0, 1);
+    slip walls in y, the left state entering on the left, open right end.
+    Returns (mesh, state)."""
+    left = primitive_to_conserved(3.857134, 2.629369, 0.0, 10.33333, gamma)
+    mesh = channel_mesh(nx, ny, split, jitter, seed, inflow=np.asarray(left), lx=10.0, ly=0.25)
+
+    def f(x, y):
+        rho = np.where(x <= 1.0, 3.857134, 1.0 + 0.2 * np.sin(5.0 * x))
+        u = np.where(x <= 1.0, 2.629369, 0.0)
+        p = np.where(x <= 1.0, 10.33333, 1.0)
+        return primitive_to_conserved(rho, u, np.zeros_like(u), p, gamma)
+    return mesh, cell_averages(mesh, f, 4, q=3)
+
+
+def shock_vortex(n: int = 100, jitter: float = 0.3, seed: int = 12, split="tri",
+                 gamma=GAMMA, mach: float = 1.1, kappa: float = 0.3, mu: float = 0.204,
+                 rc: float = 0.05, centre=(0.25, 0.5)):
+    """Shock-vortex interaction (Sec. 4.3): [0,2] x [0,1], a stationary
+    Mach 1.1 shock at x = 0.5 with upstream (rho, U, V, p) = (Ma^2, sqrt(gamma),
+    0, 1), the downstream state from the Rankine-Hugoniot relations, and the
+    vortex perturbation of the paper added upstream; slip walls top and
+    bottom, the upstream state entering on the left, open right end.
+    Returns (mesh, state)."""
+    r1, u1, p1 = mach ** 2, math.sqrt(gamma), 1.0
+    m2 = mach ** 2
+    r2 = r1 * (gamma + 1) * m2 / ((gamma - 1) * m2 + 2)
+    p2 = p1 * (2 * gamma * m2 - (gamma - 1)) / (gamma + 1)
+    u2 = r1 * u1 / r2
+    up = np.asarray(primitive_to_conserved(r1, u1, 0.0, p1, gamma))
+    mesh = channel_mesh(2 * n, n, split, jitter, seed, inflow=up, lx=2.0, ly=1.0)
+
+    def f(x, y):
+        dx, dy = x - centre[0], y - centre[1]
+        eta = np.hypot(dx, dy) / rc
+        th = np.arctan2(dy, dx)
+        amp = kappa * eta * np.exp(mu * (1 - eta * eta))
+        du, dv = amp * np.sin(th), -amp * np.cos(th)
+        dT = -(gamma - 1) * kappa ** 2 / (4 * mu * gamma) * np.exp(2 * mu * (1 - eta * eta))
+        # upstream: T = p / rho and S = ln(p / rho^gamma) fixed, T perturbed
+        T = p1 / r1 + dT
+        rho_v = (T / (p1 / r1 ** gamma)) ** (1.0 / (gamma - 1))
+        up_ = x < 0.5
+        rho = np.where(up_, rho_v, r2)
+        u = np.where(up_, u1 + du, u2)
+        v = np.where(up_, dv, 0.0)
+        p = np.where(up_, rho_v * T, p2)
+        return primitive_to_conserved(rho, u, v, p, gamma)
+    return mesh, cell_averages(mesh, f, 4, q=3)
+
+
+def cell_centres(mesh: Mesh):
+    """Vertex averages of the cells (x, y)."""
+    cn = mesh.cell_nodes
+    nf = np.where(cn[:, 3] < 0, 3, 4)
+    xy = np.where((cn >= 0)[:, :, None], mesh.node_xy[np.maximum(cn, 0)], 0.0).sum(1)
+    return xy[:, 0] / nf, xy[:, 1] / nf
+
+
 def initial_state(name: str, mesh: Mesh, q: int | None = None) -> np.ndarray:
     if name == "c1":
         return cell_averages(mesh, density_wave_scalar(0.0), 1, q=q or 5)
