@@ -137,6 +137,7 @@ struct Staged {
   std::vector<uw::Tile> tiles;
   std::vector<int32_t> tile_off, tile_ids, inst_tiles, fnb;
   std::vector<double> inflow;   // [n_states][4] prescribed states of all instances
+  int32_t special = 0;          // any wall or prescribed-state face
   int64_t rows_q = 0, rows_t = 0;
   std::vector<uint16_t> q_lidx, t_lidx;
   std::vector<double> q_Y, q_off, q_gam, q_eta, t_Y, t_off, t_gam, t_eta, fgeo;
@@ -235,6 +236,7 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
         S.fnb[c * S.N + off[k] + i] =
             p <= -3 ? p - soff
                     : p < 0 ? p : (int32_t)((((int64_t)(p >> 3) + off[k]) << 3) | (p & 7));
+        if (p <= -2) S.special = 1;
       }
     for (int c = 0; c < 12; ++c)
       std::copy(ts[k]->fgeo.begin() + c * Nk, ts[k]->fgeo.begin() + (c + 1) * Nk,
@@ -369,6 +371,7 @@ uw_status ensure_tables(Engine& E) {
   v.tri.eta = d.t_eta.template as<T>();
   v.fnb = d.fnb.template as<int32_t>();
   v.inflow = S.inflow.empty() ? nullptr : d.inflow.template as<double>();
+  v.special = S.special;
   v.fnrm = d.fnrm.template as<T>();
   v.fcoef = d.fcoef.template as<double>();
   d.ready = true;

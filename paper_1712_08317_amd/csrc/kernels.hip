@@ -144,6 +144,7 @@ __device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny,
 template <typename T, int NF, int V>
 __device__ inline void ghost_differences(const MeshDev<T>& m, int64_t i, const double* w0,
                                          T (&dW)[Layout<NF>::S - 1][V]) {
+  if (!m.special) return;   // only open and periodic boundaries: nothing to replace
 #pragma unroll
   for (int k = 0; k < NF; ++k) {
     const int32_t pk = m.fnb[k * m.N + i];

@@ -46,6 +46,7 @@ struct MeshDev {
   const int32_t* fnb = nullptr;     // [4][N] (nbr << 3) | (nbr_face << 1) | left; boundary:
                                     // -1 transmissive, -2 reflective, -3 - s prescribed state s
   const double* inflow = nullptr;   // [n_states][4] prescribed states (conserved)
+  int32_t special = 0;              // 1 if any face is a wall or takes a prescribed state
   const T* fnrm = nullptr;          // [4*2][N] canonical unit normal of each face
   const double* fcoef = nullptr;    // [4][N] |l| / (2 |Omega_i|), closed for the stored normals
 };
