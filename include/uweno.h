@@ -175,7 +175,12 @@ uw_status uw_residual(uw_mesh* mesh, const uw_physics* physics, const double* W,
 /* One step of the three-stage TVD Runge-Kutta scheme (Sec. 4), in place on
  * W.  t_dev: device double holding the time; dt = min(dt_fixed, t_end - t)
  * if dt_fixed > 0, else min(cfl * min_i 2|Omega_i| / sum_p |l_p|(|u.n_p| + c),
- * t_end - t); t_dev is advanced by dt on the device.  No host sync. */
+ * t_end - t); t_dev is advanced by dt on the device.  No host sync.  The
+ * first call with a given (W, t_dev, cfl, dt_fixed, t_end, physics) captures
+ * the step's launches into a hipGraph and later calls replay it (the null
+ * stream is served by a library stream ordered with it); while per-kernel
+ * timing is on (uw_profile) the launches are issued one by one instead.
+ * uw_precompute_geometry, uw_autotune and uw_schedule drop the graphs. */
 uw_status uw_rk3_step(uw_mesh* mesh, const uw_physics* physics, double* W, double cfl,
                       double dt_fixed, double t_end, double* t_dev, void* stream);
 

@@ -714,9 +714,12 @@ uw_status uw_rk3_step(uw_mesh* m, const uw_physics* p, double* W, double cfl, do
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(UW_EINVAL, "need cfl > 0 or dt_fixed > 0");
   UW_TRY(mesh_ready(m));
   hipStream_t st = (hipStream_t)stream;
+  // replay a captured graph of the step (one launch instead of about a dozen)
+  // unless per-kernel timing is on, which records events between launches
+  const bool graph = !m->eng.profiling;
   if (p->precision == UW_FP64)
-    return rk3_steps<double>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, false);
-  return rk3_steps<float>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, false);
+    return rk3_steps<double>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, graph);
+  return rk3_steps<float>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, graph);
 }
 
 uw_status uw_cfl_dt(uw_mesh* m, const uw_physics* p, const double* W, double cfl, double* dt_dev,

@@ -1,0 +1,55 @@
+"""Order of accuracy on the GPU: the smooth Euler density wave of the
+160k-cell workload, rho = 1 + 0.2 sin(pi(x + y - 2t)), u = v = p = 1, run to
+t = 0.5 with the device CFL step (CFL 0.5) on the full 400 x 400 quad and
+283 x 283 x 2 triangle meshes and their halvings, 20% node jitter.  The L1
+error of the density against the exact cell averages falls at third order,
+as the paper's accuracy tables report (orders 2.7-4.1 on its meshes)."""
+import numpy as np
+import pytest
+
+import workloads as wl
+from gpu_helpers import physics_for
+
+pytestmark = pytest.mark.gpu
+
+
+def _run(uw, mesh, prec, t_end=0.5):
+    import torch
+    M = uw.Mesh.from_workload(mesh, device=0)
+    M.precompute()
+    W = torch.from_numpy(M.to_internal(wl.initial_state("c2q", mesh))).to("cuda:0")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ph = physics_for(uw, "euler", prec)
+    steps = 0
+    while t.item() < t_end * (1 - 1e-14):
+        for _ in range(25):
+            M.rk3_step(ph, W, t, cfl=0.5, t_end=t_end)
+        steps += 25
+        assert steps < 20000
+    M.check()
+    return M.to_original(W.cpu().numpy()), t.item()
+
+
+@pytest.mark.parametrize("kind,sizes", [("quad", (100, 200, 400)), ("tri", (71, 142, 283))])
+def test_density_wave_converges_at_third_order(kind, sizes):
+    import paper_1712_08317_amd as uw
+    errs, hs = [], []
+    for n in sizes:
+        mesh = wl.grid_mesh(n, n, 2.0, 2.0, kind, 0.2, 2 if kind == "quad" else 3, True)
+        W, t = _run(uw, mesh, "fp64")
+        assert abs(t - 0.5) < 1e-12
+        exact = wl.cell_averages(mesh, wl.density_wave_euler(0.5), 4, q=4)
+        area = wl.signed_areas(mesh.node_xy, mesh.cell_nodes)
+        errs.append(float((area * np.abs(W[0] - exact[0])).sum() / area.sum()))
+        hs.append(2.0 / n)
+        # the velocity and pressure of the wave stay uniform
+        u = W[1] / W[0]
+        assert np.abs(u - 1).max() < 1e-9
+    orders = np.log(np.array(errs[:-1]) / np.array(errs[1:])) / np.log(np.array(hs[:-1]) / np.array(hs[1:]))
+    print(kind, "L1 errors", errs, "orders", orders, flush=True)
+    assert (orders > 2.5).all() and orders[-1] > 2.8
+    # FP32 arithmetic on the finest mesh stays within 1e-5 of FP64
+    W32, _ = _run(uw, mesh, "fp32")
+    rel = float(np.abs(W32 - W).sum() / np.abs(W).sum())
+    print(kind, "fp32 vs fp64 at t = 0.5, relative L1", rel, flush=True)
+    assert rel <= 1e-5

@@ -241,3 +241,31 @@ def test_characteristic_rk3_steps_match_oracle():
     got = M.to_original(Wd.cpu().numpy())
     print("characteristic sod rk3 rel L1", rel_l1(got, ref))
     assert rel_l1(got, ref) <= 1e-12
+
+
+def test_single_mesh_graph_replays_match_eager_steps():
+    """uw_rk3_step replays a captured graph when per-kernel timing is off and
+    launches eagerly when it is on: the two give the same bits, replay after
+    replay, with unrelated device work in between."""
+    import torch
+    uw, mesh, M, T = _setup("mixed")
+    W = wl.seeded_state(mesh, 4, 16)
+    for prec in ("fp64", "fp32"):
+        ph = physics_for(uw, "euler", prec)
+        Wg = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+        We = Wg.clone()
+        tg = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        te = tg.clone()
+        for rep in range(3):
+            M.profile(enable=0)
+            M.rk3_step(ph, Wg, tg, cfl=0.4)
+            noise = torch.randn(1000, device="cuda:0").sum()
+            torch.cuda.synchronize()
+            del noise
+            M.profile(enable=1)
+            M.rk3_step(ph, We, te, cfl=0.4)
+            M.profile(enable=0)
+            torch.cuda.synchronize()
+            assert torch.equal(Wg, We), (prec, rep)
+            assert tg.item() == te.item()
+        M.check()
