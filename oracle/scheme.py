@@ -43,7 +43,10 @@ Readings:
   momentum reversed (reflective, a slip wall), or a prescribed state
   (inflow).  The same outside state, formed from the cell average, is the
   value of the mirrored ghost cell in the face neighbour's stencil slot;
-  for scalar advection a wall is treated as transmissive;
+  for scalar advection a wall is treated as transmissive.  A moving front
+  (for the exact shock of the double Mach reflection) gives one of two
+  prescribed states by the side of a moving line on which the face
+  midpoint lies, at the time of the RK stage (t, t + dt, t + dt/2);
 * time step: dt = CFL min_i 2|Omega_i| / sum_p |l_p| (|u_i . n_p| + c_i), from
   cell averages (c = 0 and u = a for scalar advection), clamped to t_end - t.
   The paper instead fixes dt = 0.3 h for its accuracy runs.
@@ -73,7 +76,7 @@ class Physics:
 # boundary faces
 # --------------------------------------------------------------------------
 
-BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 1, 2, 3
+BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW, BC_FRONT = 1, 2, 3, 1 << 16
 
 
 def face_kind(mesh, cells, k):
@@ -87,11 +90,25 @@ def face_kind(mesh, cells, k):
     return kind
 
 
-def ghost_state(Wv, kind, nx, ny, inflow=None):
+def face_midpoints(mesh, cells, k):
+    """Midpoint (x, y) of face k of the given cells (vertex k to k + 1)."""
+    cn = np.asarray(mesh.cell_nodes)[np.asarray(cells)]
+    nf = np.where(cn[..., 3] < 0, 3, 4)
+    kk = np.minimum(k, nf - 1)
+    a = mesh.node_xy[np.take_along_axis(cn, kk[..., None], -1)[..., 0]]
+    b = mesh.node_xy[np.take_along_axis(cn, ((kk + 1) % nf)[..., None], -1)[..., 0]]
+    m = 0.5 * (a + b)
+    return m[..., 0], m[..., 1]
+
+
+def ghost_state(Wv, kind, nx, ny, inflow=None, fronts=None, pos=None, t=0.0):
     """State outside a boundary face with outward unit normal (nx, ny):
     transmissive - the inner state; reflective - the inner state with its
-    normal momentum reversed; inflow s (kind 3 + s) - prescribed state s.
-    Wv: [V, ...]; kind, nx, ny broadcast against Wv[0]."""
+    normal momentum reversed; inflow s (kind 3 + s) - prescribed state s;
+    moving front f (kind 2^16 + f, row f = (ex, ey, c0, s, A, B)) - state A
+    where the face midpoint ``pos`` lies behind the line e.x = c0 + s t at
+    time t, else state B.  Wv: [V, ...]; kind, nx, ny broadcast against
+    Wv[0]."""
     Wv = np.asarray(Wv, dtype=np.float64)
     out = Wv.copy()
     kind = np.broadcast_to(kind, Wv.shape[1:])
@@ -100,11 +117,28 @@ def ghost_state(Wv, kind, nx, ny, inflow=None):
         refl = kind == BC_REFLECTIVE
         out[1] = np.where(refl, Wv[1] - 2.0 * mn * nx, out[1])
         out[2] = np.where(refl, Wv[2] - 2.0 * mn * ny, out[2])
-    if inflow is not None and (kind >= BC_INFLOW).any():
-        st = np.asarray(inflow, dtype=np.float64)[np.maximum(kind - BC_INFLOW, 0)]  # [..., 4]
+    fixed = (kind >= BC_INFLOW) & (kind < BC_FRONT)
+    if inflow is not None and fixed.any():
+        idx = np.where(fixed, kind - BC_INFLOW, 0)
+        st = np.asarray(inflow, dtype=np.float64)[idx]                     # [..., 4]
         for v in range(Wv.shape[0]):
-            out[v] = np.where(kind >= BC_INFLOW, st[..., v], out[v])
+            out[v] = np.where(fixed, st[..., v], out[v])
+    moving = kind >= BC_FRONT
+    if fronts is not None and moving.any():
+        f = np.asarray(fronts, dtype=np.float64)[np.where(moving, kind - BC_FRONT, 0)]
+        behind = f[..., 0] * pos[0] + f[..., 1] * pos[1] < f[..., 2] + f[..., 3] * t
+        st = np.where(behind[..., None], f[..., 4:8], f[..., 8:12])
+        for v in range(Wv.shape[0]):
+            out[v] = np.where(moving, st[..., v], out[v])
     return out
+
+
+def outside_state(mesh, cells, k, Wv, nx, ny, t=0.0):
+    """ghost_state for face k of the given cells of a mesh, at time t."""
+    kind = face_kind(mesh, cells, k)
+    fronts = getattr(mesh, "fronts", None)
+    pos = face_midpoints(mesh, cells, k) if fronts is not None else None
+    return ghost_state(Wv, kind, nx, ny, getattr(mesh, "inflow", None), fronts, pos, t)
 
 
 # --------------------------------------------------------------------------
@@ -176,7 +210,7 @@ def _nonlinear_combination(gp, sp, gm, sm, beta, d, eps):
     return out                                          # [F,m,G]
 
 
-def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None):
+def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None, t=0.0):
     st = g.st
     cells = st.cells[rows]
     rc = st.runtime_cell[rows]                          # [m,S]
@@ -189,8 +223,7 @@ def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None):
         if mesh is None or not b.any():
             continue
         nrm = g.normal[rows][:, k]
-        ghost = ghost_state(W0, face_kind(mesh, cells, k), nrm[:, 0], nrm[:, 1],
-                            getattr(mesh, "inflow", None))
+        ghost = outside_state(mesh, cells, k, W0, nrm[:, 0], nrm[:, 1], t)
         dW[:, :, k + 1] = np.where(b[None], ghost - W0, dW[:, :, k + 1])
     Y = g.Y[rows]                                       # [m,M,2,2]
     off = g.gp_off[rows]                                # [m,G,2]
@@ -232,7 +265,7 @@ def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None):
     return W0[:, :, None] + inc                         # [V,m,G]
 
 
-def reconstruct_face_states(tables: Tables, W, cells=None, gamma=1.4):
+def reconstruct_face_states(tables: Tables, W, cells=None, gamma=1.4, t=0.0):
     """Reconstructed values at the 2n Gauss points of each requested cell.
 
     Returns a dict cell -> array [V, 2n] (point g = 2k + q is the q-th Gauss
@@ -250,7 +283,7 @@ def reconstruct_face_states(tables: Tables, W, cells=None, gamma=1.4):
         rows = (tables.loc[mine] & 0xFFFFFFFF).astype(np.int64)
         step = 8192
         for i in range(0, rows.size, step):
-            R = _weno_group(g, W, tables.scheme, rows[i:i + step], gamma, tables.mesh)
+            R = _weno_group(g, W, tables.scheme, rows[i:i + step], gamma, tables.mesh, t)
             for c, r in zip(mine[i:i + step], np.moveaxis(R, 1, 0)):
                 out[int(c)] = r
     return out
@@ -321,7 +354,7 @@ def _face_flux(physics, WL, WR, nx, ny):
 # residual, time step, RK3
 # --------------------------------------------------------------------------
 
-def residual(tables: Tables, W, physics: Physics, cells=None):
+def residual(tables: Tables, W, physics: Physics, cells=None, t=0.0):
     """L(W) = -(1/|Omega_i|) sum_p |l_p| sum_k (1/2) F(x_pk) . n_p for the
     requested cells (default: all).  Returns [V, len(cells)]."""
     W = np.asarray(W, dtype=np.float64)
@@ -331,7 +364,7 @@ def residual(tables: Tables, W, physics: Physics, cells=None):
     cells = np.asarray(cells, dtype=np.int64)
     nb = conn.nbr[cells]
     need = np.unique(np.concatenate([cells, nb[nb >= 0]]))
-    R = reconstruct_face_states(tables, W, need, physics.gamma)
+    R = reconstruct_face_states(tables, W, need, physics.gamma, t)
     V = W.shape[0]
     L = np.zeros((V, cells.size))
     for idx, i in enumerate(cells):
@@ -343,10 +376,8 @@ def residual(tables: Tables, W, physics: Physics, cells=None):
             if c < 0:
                 nx, ny = gi.normal[ri, k]
                 ln = gi.length[ri, k]
-                kind = face_kind(tables.mesh, [int(i)], k)[0]
-                inflow = getattr(tables.mesh, "inflow", None)
-                G0 = ghost_state(Ri[:, 2 * k], kind, nx, ny, inflow)
-                G1 = ghost_state(Ri[:, 2 * k + 1], kind, nx, ny, inflow)
+                G0 = outside_state(tables.mesh, int(i), k, Ri[:, 2 * k], nx, ny, t)
+                G1 = outside_state(tables.mesh, int(i), k, Ri[:, 2 * k + 1], nx, ny, t)
                 F0 = _face_flux(physics, Ri[:, 2 * k], G0, nx, ny)
                 F1 = _face_flux(physics, Ri[:, 2 * k + 1], G1, nx, ny)
                 acc += ln * 0.5 * (F0 + F1)
@@ -370,7 +401,7 @@ def residual(tables: Tables, W, physics: Physics, cells=None):
     return L
 
 
-def residual_vectorized(tables: Tables, W, physics: Physics):
+def residual_vectorized(tables: Tables, W, physics: Physics, t=0.0):
     """Same as ``residual`` for all cells, vectorised over cells per face slot
     (used for large meshes; identical arithmetic per face)."""
     W = np.asarray(W, dtype=np.float64)
@@ -387,7 +418,7 @@ def residual_vectorized(tables: Tables, W, physics: Physics):
         for i in range(0, cells.size, step):
             rows = np.arange(i, min(cells.size, i + step))
             R[:, cells[rows], :2 * nf_value] = _weno_group(g, W, tables.scheme, rows,
-                                                           physics.gamma, tables.mesh)
+                                                           physics.gamma, tables.mesh, t)
         normal[cells] = g.normal
         length[cells] = g.length
         area[cells] = g.area
@@ -408,10 +439,8 @@ def residual_vectorized(tables: Tables, W, physics: Physics):
         nL = np.where((left | bnd)[:, None], normal[:, k], normal[cc, kk])
         nL = np.where(valid[:, None], nL, 1.0 / np.sqrt(2.0))
         # outside of a boundary face: its ghost state
-        kind = face_kind(tables.mesh, ids, k)
-        inflow = getattr(tables.mesh, "inflow", None)
-        G0 = ghost_state(Ri0, kind, nL[:, 0], nL[:, 1], inflow)
-        G1 = ghost_state(Ri1, kind, nL[:, 0], nL[:, 1], inflow)
+        G0 = outside_state(tables.mesh, ids, k, Ri0, nL[:, 0], nL[:, 1], t)
+        G1 = outside_state(tables.mesh, ids, k, Ri1, nL[:, 0], nL[:, 1], t)
         Rc0 = np.where(inn[None], R[:, cc, 2 * kk + 1], G0)    # neighbour value at my point 0
         Rc1 = np.where(inn[None], R[:, cc, 2 * kk], G1)
         lL = np.where(left | bnd, length[:, k], length[cc, kk])
@@ -452,10 +481,18 @@ def cfl_dt(tables: Tables, W, physics: Physics, cfl: float):
     return cfl * best
 
 
-def rk3_step(tables: Tables, W, physics: Physics, dt: float, resid=None):
-    """One step of the three-stage TVD Runge-Kutta scheme of Sec. 4."""
-    resid = resid or (lambda X: residual_vectorized(tables, X, physics))
+def rk3_step(tables: Tables, W, physics: Physics, dt: float, resid=None, t=0.0):
+    """One step of the three-stage TVD Runge-Kutta scheme of Sec. 4 from
+    time t; the stages evaluate time-dependent boundaries at t, t + dt and
+    t + dt/2 (the times the stages approximate)."""
+    if resid is None:
+        def resid(X, tt):
+            return residual_vectorized(tables, X, physics, tt)
+        r = resid
+    else:
+        def r(X, tt):
+            return resid(X)
     Wn = np.asarray(W, dtype=np.float64)
-    W1 = Wn + dt * resid(Wn)
-    W2 = 0.75 * Wn + 0.25 * (W1 + dt * resid(W1))
-    return Wn / 3.0 + 2.0 / 3.0 * (W2 + dt * resid(W2))
+    W1 = Wn + dt * r(Wn, t)
+    W2 = 0.75 * Wn + 0.25 * (W1 + dt * r(W1, t + dt))
+    return Wn / 3.0 + 2.0 / 3.0 * (W2 + dt * r(W2, t + 0.5 * dt))

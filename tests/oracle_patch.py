@@ -101,13 +101,13 @@ def patch_mesh(mesh, inc: NodeIncidence, centre_cell: int, rings: int):
     sub = wl.Mesh(node_xy=np.array(node_xy, dtype=np.float64), cell_nodes=out, node_id=None,
                   period=(0.0, 0.0), bc="transmissive", h=mesh.h, name=f"patch{centre_cell}",
                   face_bc=None if fbc is None else np.asarray(fbc)[cells],
-                  inflow=getattr(mesh, "inflow", None))
+                  inflow=getattr(mesh, "inflow", None), fronts=getattr(mesh, "fronts", None))
     return sub, cells
 
 
-def rk3_at(mesh, W, samples, physics, dt, steps=1, inc=None, scheme=None):
-    """Oracle state after ``steps`` RK3 steps of fixed ``dt`` at the sampled
-    cells (original ids): array [nvar, len(samples)]."""
+def rk3_at(mesh, W, samples, physics, dt, steps=1, inc=None, scheme=None, t0=0.0):
+    """Oracle state after ``steps`` RK3 steps of fixed ``dt`` from time t0 at
+    the sampled cells (original ids): array [nvar, len(samples)]."""
     inc = inc or NodeIncidence(mesh)
     rings = RK3_RINGS * steps
     out = np.empty((W.shape[0], len(samples)))
@@ -118,27 +118,27 @@ def rk3_at(mesh, W, samples, physics, dt, steps=1, inc=None, scheme=None):
             # a small periodic mesh: the whole-mesh oracle answers directly
             T = ow.precompute(mesh, scheme)
             Wt = W.copy()
-            for _ in range(steps):
-                Wt = osc.rk3_step(T, Wt, physics, dt)
+            for k in range(steps):
+                Wt = osc.rk3_step(T, Wt, physics, dt, t=t0 + k * dt)
             return Wt[:, np.asarray(samples)]
         T = ow.precompute(sub, scheme)
         Ws = W[:, cells].copy()
         # cells at the patch edge see truncated stencils and may leave the
         # admissible set; they are out of the sampled cell's reach
         with np.errstate(invalid="ignore", divide="ignore"):
-            for _ in range(steps):
-                Ws = osc.rk3_step(T, Ws, physics, dt)
+            for k in range(steps):
+                Ws = osc.rk3_step(T, Ws, physics, dt, t=t0 + k * dt)
         out[:, s] = Ws[:, np.searchsorted(cells, c)]
     return out
 
 
-def residual_at(mesh, W, samples, physics, inc=None, scheme=None):
-    """Oracle residual L(W) at the sampled cells (three rings suffice)."""
+def residual_at(mesh, W, samples, physics, inc=None, scheme=None, t=0.0):
+    """Oracle residual L(W) at time t at the sampled cells (three rings suffice)."""
     inc = inc or NodeIncidence(mesh)
     out = np.empty((W.shape[0], len(samples)))
     for s, c in enumerate(samples):
         sub, cells = patch_mesh(mesh, inc, int(c), 3)
         T = ow.precompute(sub, scheme)
-        L = osc.residual_vectorized(T, W[:, cells], physics)
+        L = osc.residual_vectorized(T, W[:, cells], physics, t=t)
         out[:, s] = L[:, np.searchsorted(cells, c)]
     return out

@@ -135,3 +135,42 @@ def test_mixed_kinds_on_one_mesh():
     # with vertical velocity the walls act: not steady any more
     W2 = np.tile(_prim(1.0, 2.0, 0.5, 1.0)[:, None], (1, mesh.n_cells))
     assert np.abs(osc.residual_vectorized(T, W2, osc.Physics("euler"))).max() > 1e-3
+
+
+def test_moving_front_picks_the_state_by_side_and_time():
+    """A front row (ex, ey, c0, s, A, B): state A where e.x < c0 + s t."""
+    A = _prim(8.0, 7.0, -4.0, 116.5)
+    B = _prim(1.4, 0.0, 0.0, 1.0)
+    fronts = np.concatenate([[1.0, 0.0, 0.5, 2.0], A, B])[None, :]
+    x = np.array([0.1, 0.6, 0.9, 1.6])
+    W = np.tile(_prim(1.0, 0.0, 0.0, 1.0)[:, None], (1, 4))
+    kind = np.full(4, osc.BC_FRONT)
+    for t, behind in ((0.0, [1, 0, 0, 0]), (0.2, [1, 1, 0, 0]), (0.5, [1, 1, 1, 0])):
+        G = osc.ghost_state(W, kind, np.zeros(4), np.ones(4), None, fronts, (x, np.ones(4)), t)
+        exp = np.where(np.array(behind, bool)[None, :], A[:, None], B[:, None])
+        assert np.array_equal(G, exp), t
+
+
+def test_double_mach_boundaries_follow_the_exact_shock():
+    """The double Mach reflection set-up: at any time the top boundary's
+    outside state is the exact solution there (post-shock behind the shock
+    line x = 1/6 + (1 + 20 t)/sqrt3), the bottom carries the post-shock
+    state before x = 1/6 and is a wall after it, and the initial state is the
+    exact one; residuals at two times differ only next to the top."""
+    mesh, W = wl.double_mach(nx=48, ny=12)
+    post, pre = mesh.inflow[0], mesh.fronts[0, 8:12]
+    cx, cy = wl.cell_centres(mesh)
+    assert np.array_equal(W[:, cx < 1 / 6 + cy / np.sqrt(3)][:, :1], post[:, None])
+    top = np.flatnonzero(mesh.face_bc.max(axis=1) >= wl.BC_FRONT)
+    for t in (0.0, 0.05):
+        for c in top:
+            k = int(np.argmax(mesh.face_bc[c] >= wl.BC_FRONT))
+            mx, my = osc.face_midpoints(mesh, [c], k)
+            G = osc.outside_state(mesh, [c], k, W[:, [c]], 0.0, 1.0, t)[:, 0]
+            exact = post if mx[0] < 1 / 6 + (my[0] + 20 * t) / np.sqrt(3) else pre
+            assert np.array_equal(G, exact)
+    T = ow.precompute(mesh)
+    L0 = osc.residual_vectorized(T, W, osc.Physics("euler"), t=0.0)
+    L1 = osc.residual_vectorized(T, W, osc.Physics("euler"), t=0.05)
+    changed = np.flatnonzero(np.abs(L1 - L0).max(0) > 0)
+    assert changed.size > 0 and (cy[changed] > 1 - 4 * mesh.h).all()

@@ -51,6 +51,7 @@ class Mesh:
     # and the prescribed states that BC_INFLOW + s refers to [n_states, 4]
     face_bc: np.ndarray | None = None
     inflow: np.ndarray | None = None
+    fronts: np.ndarray | None = None      # [n_fronts, 12] moving fronts (see BC_FRONT)
 
     @property
     def n_cells(self) -> int:
@@ -64,8 +65,9 @@ class Mesh:
         return np.where(self.cell_nodes[:, 3] < 0, 3, 4).astype(np.int32)
 
 
-# boundary kinds of unmatched faces (input description only)
-BC_DEFAULT, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW = 0, 1, 2, 3
+# boundary kinds of unmatched faces (input description only); a moving
+# front f is BC_FRONT + f, its row in mesh.fronts = (ex, ey, c0, s, A, B)
+BC_DEFAULT, BC_TRANSMISSIVE, BC_REFLECTIVE, BC_INFLOW, BC_FRONT = 0, 1, 2, 3, 1 << 16
 
 
 # --------------------------------------------------------------------------
@@ -490,6 +492,38 @@ def shock_vortex(n: int = 100, jitter: float = 0.3, seed: int = 12, split="tri",
         p = np.where(up_, rho_v * T, p2)
         return primitive_to_conserved(rho, u, v, p, gamma)
     return mesh, cell_averages(mesh, f, 4, q=3)
+
+
+def double_mach(nx: int = 400, ny: int = 100, split="tri", jitter: float = 0.15, seed: int = 13,
+                gamma=GAMMA):
+    """Double Mach reflection (Sec. 4.4): [0,4] x [0,1], a Mach 10 shock
+    through (1/6, 0) at 60 degrees to the x-axis, post-shock state
+    (8, 4.125 sqrt3, -4.125, 116.5) behind it and (1.4, 0, 0, 1) ahead.  The
+    bottom is a slip wall from x = 1/6 on and carries the post-shock state
+    before it, the left end takes the post-shock state, the right end is
+    open, and the top follows the exact shock: post-shock where
+    x < 1/6 + (1 + 20 t)/sqrt3, else pre-shock.  Returns (mesh, state)."""
+    post = np.asarray(primitive_to_conserved(8.0, 4.125 * math.sqrt(3.0), -4.125, 116.5, gamma))
+    pre = np.asarray(primitive_to_conserved(1.4, 0.0, 0.0, 1.0, gamma))
+    mesh = grid_mesh(nx, ny, 4.0, 1.0, split, jitter, seed, False, name=f"dmr{nx}x{ny}")
+    x0, r3 = 1.0 / 6.0, math.sqrt(3.0)
+    tol = 1e-9
+
+    def kind_of(mx, my, nx_, ny_):
+        bottom = np.abs(my) < tol
+        top = np.abs(my - 1.0) < tol
+        left = np.abs(mx) < tol
+        k = np.full(mx.shape, BC_TRANSMISSIVE)
+        k = np.where(left, BC_INFLOW, k)
+        k = np.where(bottom, np.where(mx < x0, BC_INFLOW, BC_REFLECTIVE), k)
+        return np.where(top, BC_FRONT, k)
+    set_face_kinds(mesh, kind_of)
+    mesh.inflow = post[None, :].copy()
+    mesh.fronts = np.concatenate([[1.0, 0.0, x0 + 1.0 / r3, 20.0 / r3], post, pre])[None, :]
+    cx, cy = cell_centres(mesh)
+    behind = cx < x0 + cy / r3
+    W = np.where(behind[None, :], post[:, None], pre[:, None])
+    return mesh, W
 
 
 def cell_centres(mesh: Mesh):
