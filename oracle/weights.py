@@ -24,7 +24,13 @@ Readings:
   constraint on i0 holds exactly and the two remaining constraints give a
   2x2 regularised solve g = Y (dW_a, dW_b);
 * the optimisation weights are taken per Gauss point from that point's
-  unoptimised gamma (one pass, not iterated).
+  unoptimised gamma (one pass, not iterated);
+* optimised weights of magnitude below 1e-10 are set to zero.  Such weights
+  arise for degenerate candidates (whose third cell is the target cell after
+  substitution, next to a boundary) as the rounding residue of O(1) terms,
+  with no significant digit; kept, a rounding-level weight on a candidate
+  whose indicator is zero (a field that is constant across a wall, say)
+  outweighs every other candidate and the result follows the rounding.
 """
 from __future__ import annotations
 
@@ -49,6 +55,9 @@ class Scheme:
 
 
 RANK_TOL = 1e-12
+# linear weights below this magnitude are zero: formed from O(1) quantities,
+# they carry no significant digit (degenerate candidates next to boundaries)
+GAMMA_ZERO = 1e-10
 
 
 def tikhonov(Mat, zeta):
@@ -159,6 +168,9 @@ def _group(mesh, conn, nf_value, cells, scheme: Scheme) -> Group:
         gamma = np.einsum("mgjs,mgs->mgj", PB, eta)
     else:
         eta, gamma = eta_raw, gamma_raw
+    # a weight at rounding level would otherwise take over the nonlinear
+    # weights wherever its candidate is smooth and the others are not
+    gamma = np.where(np.abs(gamma) < GAMMA_ZERO, 0.0, gamma)
 
     return Group(st=st, frame=fr, cand_a=cand_a, cand_b=cand_b, Y=Y, gp_off=off,
                  eta=eta, gamma=gamma, eta_raw=eta_raw, gamma_raw=gamma_raw, B=B,

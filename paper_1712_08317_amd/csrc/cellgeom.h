@@ -19,7 +19,11 @@
 // * the candidate fit keeps the zero-mean form W_i0 + g.(p^1, p^2) and solves
 //   the two remaining constraints for g (a 2x2 regularised solve);
 // * the optimisation weights d come from each Gauss point's own unoptimised
-//   weights (or the largest over the cell's points), one pass.
+//   weights (or the largest over the cell's points), one pass;
+// * optimised weights below 1e-10 in magnitude are zero: they are rounding
+//   residue of O(1) terms (degenerate candidates next to boundaries), and a
+//   rounding-level weight on a candidate with a zero smoothness indicator
+//   would outweigh every other candidate in the nonlinear weights.
 #pragma once
 
 #include <cmath>
@@ -35,6 +39,7 @@ namespace uw {
 namespace geom {
 
 constexpr double kRankTol = 1e-12;
+constexpr double kGammaZero = 1e-10;
 // Gauss points of eq. (quadrature): (3 +- sqrt3)/6
 constexpr double kGA = 0.78867513459481288225457439025097872782380087563506;
 constexpr double kGB = 0.21132486540518711774542560974902127217619912436494;
@@ -430,6 +435,8 @@ UW_HD inline void precompute_cell(const CellIn& in, const TypeC& TQ, const TypeC
         gam[j] = s;
       }
     }
+    for (int j = 0; j < M; ++j)
+      if (fabs(gam[j]) < kGammaZero) gam[j] = 0.0;
     // diagnostics
     double sg = 0.0;
     for (int q = 0; q < S; ++q) {

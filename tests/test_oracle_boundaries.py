@@ -4,6 +4,8 @@ carries pressure only, a closed box conserves mass and energy exactly and
 keeps gas at rest at rest, a face with supersonic inflow on both sides
 passes exactly the prescribed state's flux, and a domain filled with the
 inflow state is steady."""
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -174,3 +176,29 @@ def test_double_mach_boundaries_follow_the_exact_shock():
     L1 = osc.residual_vectorized(T, W, osc.Physics("euler"), t=0.05)
     changed = np.flatnonzero(np.abs(L1 - L0).max(0) > 0)
     assert changed.size > 0 and (cy[changed] > 1 - 4 * mesh.h).all()
+
+
+def _wall_states(mesh, W, cells, t):
+    T = ow.precompute(mesh, ow.Scheme(variables="characteristic"))
+    FS = osc.reconstruct_face_states(T, W, cells, t=t)
+    return np.stack([FS[c] for c in cells])
+
+
+def test_wall_reconstruction_does_not_follow_rounding():
+    """The reconstruction is a continuous function of the geometry: moving
+    every node by a few units in the last place changes the Gauss-point
+    states next to the double Mach wall by rounding only.  (There, degenerate
+    candidates get linear weights that are zero up to rounding, and in the
+    field that is constant across a slip wall their indicator is exactly
+    zero; a weight left at rounding level would carry the result.)"""
+    mesh, W = wl.double_mach(nx=48, ny=12)
+    T = ow.precompute(mesh, ow.Scheme(variables="characteristic"))
+    t0, dt = 0.0034, 0.2 * mesh.h / 20.0
+    W1 = W + dt * osc.residual_vectorized(T, W, osc.Physics("euler"), t=t0)
+    cx, cy = wl.cell_centres(mesh)
+    cells = np.flatnonzero(cy < mesh.h)
+    moved = dataclasses.replace(mesh, node_xy=mesh.node_xy * (
+        1.0 + 4e-16 * np.random.default_rng(5).standard_normal(mesh.node_xy.shape)))
+    a = _wall_states(mesh, W1, cells, t0 + dt)
+    b = _wall_states(moved, W1, cells, t0 + dt)
+    assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
