@@ -481,17 +481,19 @@ def cfl_dt(tables: Tables, W, physics: Physics, cfl: float):
     return cfl * best
 
 
-def rk3_step(tables: Tables, W, physics: Physics, dt: float, resid=None, t=0.0):
+def rk3_step(tables: Tables, W, physics: Physics, dt: float, resid=None, t=0.0, resid_t=None):
     """One step of the three-stage TVD Runge-Kutta scheme of Sec. 4 from
     time t; the stages evaluate time-dependent boundaries at t, t + dt and
-    t + dt/2 (the times the stages approximate)."""
-    if resid is None:
-        def resid(X, tt):
-            return residual_vectorized(tables, X, physics, tt)
-        r = resid
-    else:
+    t + dt/2 (the times the stages approximate).  resid(X) or resid_t(X, t)
+    replace the scheme's residual (for tests of the integrator alone)."""
+    if resid_t is not None:
+        r = resid_t
+    elif resid is not None:
         def r(X, tt):
             return resid(X)
+    else:
+        def r(X, tt):
+            return residual_vectorized(tables, X, physics, tt)
     Wn = np.asarray(W, dtype=np.float64)
     W1 = Wn + dt * r(Wn, t)
     W2 = 0.75 * Wn + 0.25 * (W1 + dt * r(W1, t + dt))

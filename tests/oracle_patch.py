@@ -117,17 +117,20 @@ def rk3_at(mesh, W, samples, physics, dt, steps=1, inc=None, scheme=None, t0=0.0
         except PatchTooLarge:
             # a small periodic mesh: the whole-mesh oracle answers directly
             T = ow.precompute(mesh, scheme)
-            Wt = W.copy()
-            for k in range(steps):
-                Wt = osc.rk3_step(T, Wt, physics, dt, t=t0 + k * dt)
+            Wt, t = W.copy(), t0
+            for _ in range(steps):
+                Wt = osc.rk3_step(T, Wt, physics, dt, t=t)
+                t = t + dt
             return Wt[:, np.asarray(samples)]
         T = ow.precompute(sub, scheme)
         Ws = W[:, cells].copy()
         # cells at the patch edge see truncated stencils and may leave the
         # admissible set; they are out of the sampled cell's reach
         with np.errstate(invalid="ignore", divide="ignore"):
-            for k in range(steps):
-                Ws = osc.rk3_step(T, Ws, physics, dt, t=t0 + k * dt)
+            t = t0
+            for _ in range(steps):
+                Ws = osc.rk3_step(T, Ws, physics, dt, t=t)
+                t = t + dt   # the time is accumulated step by step
         out[:, s] = Ws[:, np.searchsorted(cells, c)]
     return out
 

@@ -174,6 +174,20 @@ def test_rk3_stability_polynomial():
     np.testing.assert_allclose(out[:, 0], [ref.real, ref.imag], rtol=1e-15, atol=1e-15)
 
 
+def test_rk3_stage_times_integrate_cubics_exactly():
+    """The stages of a step from t sit at t, t + dt and t + dt/2 with
+    effective weights 1/6, 1/6 and 2/3: for a right-hand side that depends on
+    time only, a step is Simpson's rule, exact for cubics.  Other stage
+    times (say t + dt for the third stage) miss y' = 4 t^3 by O(dt^3)."""
+    t0, dt = 0.3, 0.2
+    out = osc.rk3_step(None, np.array([[2.0]]), None, dt,
+                       resid_t=lambda X, tt: np.full_like(X, 4.0 * tt ** 3), t=t0)
+    assert abs(out[0, 0] - (2.0 + (t0 + dt) ** 4 - t0 ** 4)) < 1e-15
+    quad = osc.rk3_step(None, np.array([[0.0]]), None, dt,
+                        resid_t=lambda X, tt: np.full_like(X, 3.0 * tt ** 2), t=t0)
+    assert abs(quad[0, 0] - ((t0 + dt) ** 3 - t0 ** 3)) < 1e-15
+
+
 def test_cfl_on_uniform_squares():
     mesh = wl.grid_mesh(8, 8, 2.0, 2.0, "quad", 0.0, 1, True)
     T = ow.precompute(mesh)
