@@ -43,7 +43,13 @@ typedef enum {
   UW_ENONFINITE = 6   /* device flagged NaN/Inf or rho <= 0 / p <= 0             */
 } uw_status;
 
-enum { UW_BC_PERIODIC = 0, UW_BC_TRANSMISSIVE = 1, UW_BC_REFLECTIVE = 2, UW_BC_INFLOW = 3 };
+enum {
+  UW_BC_PERIODIC = 0,
+  UW_BC_TRANSMISSIVE = 1,
+  UW_BC_REFLECTIVE = 2,
+  UW_BC_INFLOW = 3,
+  UW_BC_FRONT = 1 << 16
+};
 enum { UW_WENO = 0, UW_LINEAR = 1 };
 enum { UW_CONSERVED = 0, UW_CHARACTERISTIC = 1 };
 enum { UW_D_PER_GP = 0, UW_D_PER_CELL = 1 };
@@ -68,13 +74,25 @@ typedef struct uw_batch uw_batch;
  *             UW_BC_TRANSMISSIVE, UW_BC_REFLECTIVE (slip wall: the ghost and
  *             the outside state of the face flux are the inner state with its
  *             normal momentum reversed; transmissive for scalar advection),
- *             UW_BC_INFLOW + s (prescribed conserved state s of inflow_W).
+ *             UW_BC_INFLOW + s (prescribed conserved state s of inflow_W),
+ *             UW_BC_FRONT + f (moving front f of `fronts`).
  *             The paper's tests name non-reflecting, reflective and
- *             prescribed-state boundaries (Sec. 4) without defining them.
- * n_inflow, inflow_W  number and values [n_inflow][4] (rho, rho u, rho v,
- *             rho E; advection uses the first) of the prescribed states.
+ *             prescribed-state boundaries (Sec. 4) without defining them;
+ *             the double Mach reflection's top boundary follows the exact
+ *             motion of its shock, which a moving front describes.
+ * n_inflow, inflow_W  number (<= 65533) and values [n_inflow][4] (rho,
+ *             rho u, rho v, rho E; advection uses the first) of the
+ *             prescribed states.
+ * n_fronts, fronts  number (<= 2^20) and rows [n_fronts][12] = (ex, ey, c0,
+ *             s, A[4], B[4]) of the moving fronts: at time t the outside
+ *             state of a front face is state A if e.m < c0 + s t, m the
+ *             face's midpoint (the mean of its two nodes as given), else
+ *             state B.  Inside a Runge-Kutta step from t with step dt the
+ *             three stages see the times t, t + dt and t + dt/2; e.m is
+ *             formed in FP64 without fused multiply-adds, as is c0 + s t.
  * Errors: an unmatched face whose kind is UW_BC_PERIODIC gives UW_EMESH; a
- * kind outside the list or an inflow index >= n_inflow gives UW_EINVAL. */
+ * kind outside the list, an inflow index >= n_inflow or a front index >=
+ * n_fronts gives UW_EINVAL. */
 typedef struct {
   int64_t n_nodes;
   const double* node_xy;
@@ -85,6 +103,8 @@ typedef struct {
   const int32_t* face_bc;
   int32_t n_inflow;
   const double* inflow_W;
+  int32_t n_fronts;
+  const double* fronts;
 } uw_mesh_desc;
 
 /* Scheme constants (paper Sec. 3): zeta of eq. (quadratic-2) (1e-14), theta
@@ -171,6 +191,11 @@ uw_status uw_mesh_table(const uw_mesh* mesh, int32_t which, double* out);
  * Errors: UW_ESTATE (no precompute), UW_EINVAL, UW_EDEVICE. */
 uw_status uw_residual(uw_mesh* mesh, const uw_physics* physics, const double* W, double* L,
                       void* stream);
+
+/* uw_residual at time t (host value): only moving-front faces depend on
+ * it; uw_residual is this call at t = 0. */
+uw_status uw_residual_at(uw_mesh* mesh, const uw_physics* physics, const double* W, double* L,
+                         double t, void* stream);
 
 /* One step of the three-stage TVD Runge-Kutta scheme (Sec. 4), in place on
  * W.  t_dev: device double holding the time; dt = min(dt_fixed, t_end - t)

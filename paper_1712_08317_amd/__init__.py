@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("UWENO_LIB", os.path.join(HERE, "libuweno.so"))
 
 UW_OK, UW_EINVAL, UW_EMESH, UW_ESTATE, UW_ENOMEM, UW_EDEVICE, UW_ENONFINITE = range(7)
 UW_BC_PERIODIC, UW_BC_TRANSMISSIVE, UW_BC_REFLECTIVE, UW_BC_INFLOW = 0, 1, 2, 3
+UW_BC_FRONT = 1 << 16
 UW_WENO, UW_LINEAR = 0, 1
 UW_CONSERVED, UW_CHARACTERISTIC = 0, 1
 UW_D_PER_GP, UW_D_PER_CELL = 0, 1
@@ -39,7 +40,8 @@ class MeshDesc(ctypes.Structure):
                 ("n_cells", ctypes.c_int64), ("cell_nodes", ctypes.c_void_p),
                 ("node_id", ctypes.c_void_p), ("bc", ctypes.c_int32),
                 ("face_bc", ctypes.c_void_p), ("n_inflow", ctypes.c_int32),
-                ("inflow_W", ctypes.c_void_p)]
+                ("inflow_W", ctypes.c_void_p), ("n_fronts", ctypes.c_int32),
+                ("fronts", ctypes.c_void_p)]
 
 
 class SchemeC(ctypes.Structure):
@@ -60,7 +62,8 @@ class DiagC(ctypes.Structure):
 
 
 EXPORTS = ["uw_last_error", "uw_mesh_upload", "uw_mesh_info", "uw_mesh_export",
-           "uw_precompute_geometry", "uw_mesh_table", "uw_residual", "uw_rk3_step", "uw_cfl_dt",
+           "uw_precompute_geometry", "uw_mesh_table", "uw_residual", "uw_residual_at", "uw_rk3_step",
+           "uw_cfl_dt",
            "uw_batch_create", "uw_batch_offsets", "uw_batch_rk3_step", "uw_autotune", "uw_check",
            "uw_profile", "uw_schedule", "uw_mesh_destroy", "uw_batch_destroy"]
 
@@ -81,6 +84,7 @@ def _load():
         "uw_precompute_geometry": (i32, [vp, ctypes.POINTER(SchemeC), ctypes.POINTER(DiagC)]),
         "uw_mesh_table": (i32, [vp, i32, vp]),
         "uw_residual": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, vp]),
+        "uw_residual_at": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, dbl, vp]),
         "uw_rk3_step": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, dbl, dbl, vp, vp]),
         "uw_cfl_dt": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, vp, vp]),
         "uw_batch_create": (i32, [vp, i32, ctypes.POINTER(PhysicsC), ctypes.POINTER(vp)]),
@@ -140,18 +144,22 @@ class Mesh:
     """A mesh uploaded to the library (internal Hilbert numbering)."""
 
     def __init__(self, node_xy, cell_nodes, node_id=None, bc=UW_BC_PERIODIC, device=0,
-                 face_bc=None, inflow=None):
+                 face_bc=None, inflow=None, fronts=None):
         self._xy = np.ascontiguousarray(node_xy, dtype=np.float64)
         self._cn = np.ascontiguousarray(cell_nodes, dtype=np.int32)
         self._nid = None if node_id is None else np.ascontiguousarray(node_id, dtype=np.int32)
         self._fbc = None if face_bc is None else np.ascontiguousarray(face_bc, dtype=np.int32)
         self._inf = (None if inflow is None
                      else np.ascontiguousarray(np.asarray(inflow, dtype=np.float64).reshape(-1, 4)))
+        self._fr = (None if fronts is None
+                    else np.ascontiguousarray(np.asarray(fronts, dtype=np.float64).reshape(-1, 12)))
         desc = MeshDesc(self._xy.shape[0], self._xy.ctypes.data, self._cn.shape[0],
                         self._cn.ctypes.data, None if self._nid is None else self._nid.ctypes.data,
                         bc, None if self._fbc is None else self._fbc.ctypes.data,
                         0 if self._inf is None else self._inf.shape[0],
-                        None if self._inf is None else self._inf.ctypes.data)
+                        None if self._inf is None else self._inf.ctypes.data,
+                        0 if self._fr is None else self._fr.shape[0],
+                        None if self._fr is None else self._fr.ctypes.data)
         h = ctypes.c_void_p()
         _check(LIB.uw_mesh_upload(ctypes.byref(desc), device, ctypes.byref(h)))
         self.handle = h
@@ -171,7 +179,8 @@ class Mesh:
     def from_workload(cls, mesh, device=0):
         bc = UW_BC_PERIODIC if mesh.bc == "periodic" else UW_BC_TRANSMISSIVE
         return cls(mesh.node_xy, mesh.cell_nodes, mesh.node_id, bc, device,
-                   getattr(mesh, "face_bc", None), getattr(mesh, "inflow", None))
+                   getattr(mesh, "face_bc", None), getattr(mesh, "inflow", None),
+                   getattr(mesh, "fronts", None))
 
     def __del__(self):
         h = getattr(self, "handle", None)
@@ -208,9 +217,14 @@ class Mesh:
     def to_original(self, W):
         return np.asarray(W)[:, self.new_of_old]
 
-    def residual(self, physics: PhysicsC, W, L, stream=None):
-        _check(LIB.uw_residual(self.handle, ctypes.byref(physics), _ptr(W), _ptr(L),
-                               _stream(stream)))
+    def residual(self, physics: PhysicsC, W, L, stream=None, t=None):
+        """L = L(W); at time t (moving-front boundaries) when t is given."""
+        if t is None:
+            _check(LIB.uw_residual(self.handle, ctypes.byref(physics), _ptr(W), _ptr(L),
+                                   _stream(stream)))
+        else:
+            _check(LIB.uw_residual_at(self.handle, ctypes.byref(physics), _ptr(W), _ptr(L),
+                                      float(t), _stream(stream)))
 
     def rk3_step(self, physics: PhysicsC, W, t_dev, cfl=0.5, dt_fixed=0.0, t_end=float("inf"),
                  stream=None):

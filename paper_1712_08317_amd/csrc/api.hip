@@ -137,7 +137,11 @@ struct Staged {
   std::vector<uw::Tile> tiles;
   std::vector<int32_t> tile_off, tile_ids, inst_tiles, fnb;
   std::vector<double> inflow;   // [n_states][4] prescribed states of all instances
-  int32_t special = 0;          // any wall or prescribed-state face
+  std::vector<double> fronts;   // [n_fronts][12] moving fronts of all instances
+  std::vector<int32_t> front_inst;   // [n_fronts] their instances
+  std::vector<int32_t> ff_front;   // [n_front_faces] front of each front face
+  std::vector<double> ff_proj;     // [n_front_faces] e.m of its midpoint
+  int32_t special = 0;          // any wall, prescribed-state or front face
   int64_t rows_q = 0, rows_t = 0;
   std::vector<uint16_t> q_lidx, t_lidx;
   std::vector<double> q_Y, q_off, q_gam, q_eta, t_Y, t_off, t_gam, t_eta, fgeo;
@@ -223,13 +227,18 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
       cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.eta; },
                R, ro, q ? S.q_eta : S.t_eta);
   }
-  // face tables; prescribed states of all instances in one table
+  // face tables; prescribed states, fronts and front faces of all
+  // instances in one table each
   S.fnb.assign(4 * S.N, -1);
   S.fgeo.assign(12 * S.N, 0.0);
   for (int k = 0; k < n; ++k) {
     const int64_t Nk = ms[k]->N;
     const int32_t soff = (int32_t)(S.inflow.size() / 4);
+    const int32_t foff = (int32_t)(S.fronts.size() / 12);
+    const int32_t joff = (int32_t)S.ff_front.size();
     S.inflow.insert(S.inflow.end(), ms[k]->inflow.begin(), ms[k]->inflow.end());
+    S.fronts.insert(S.fronts.end(), ms[k]->fronts.begin(), ms[k]->fronts.end());
+    S.front_inst.resize(S.fronts.size() / 12, k);
     for (int c = 0; c < 4; ++c)
       for (int64_t i = 0; i < Nk; ++i) {
         const int32_t p = ts[k]->fnb[c * Nk + i];
@@ -238,6 +247,12 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
                     : p < 0 ? p : (int32_t)((((int64_t)(p >> 3) + off[k]) << 3) | (p & 7));
         if (p <= -2) S.special = 1;
       }
+    for (size_t j = 0; j < ms[k]->ff_face.size(); ++j) {
+      const int64_t i = ms[k]->ff_face[j] / 4, c = ms[k]->ff_face[j] % 4;
+      S.fnb[c * S.N + off[k] + i] = uw::kFrontCode - (joff + (int32_t)j);
+      S.ff_front.push_back(ms[k]->ff_front[j] + foff);
+      S.ff_proj.push_back(ms[k]->ff_proj[j]);
+    }
     for (int c = 0; c < 12; ++c)
       std::copy(ts[k]->fgeo.begin() + c * Nk, ts[k]->fgeo.begin() + (c + 1) * Nk,
                 S.fgeo.begin() + c * S.N + off[k]);
@@ -248,12 +263,12 @@ template <class T>
 struct DevTables {
   bool ready = false;
   DevBuf tiles, tile_off, tile_ids, inst_tiles, q_li, q_Y, q_off, q_gam, q_eta, t_li, t_Y, t_off,
-      t_gam, t_eta, fnb, fnrm, fcoef, inflow;
+      t_gam, t_eta, fnb, fnrm, fcoef, inflow, fronts, front_inst, ff_front, ff_proj;
   uw::MeshDev<T> view;
   void reset() {
     for (DevBuf* b : {&tiles, &tile_off, &tile_ids, &inst_tiles, &q_li, &q_Y, &q_off, &q_gam,
                       &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fnrm, &fcoef,
-                      &inflow})
+                      &inflow, &fronts, &front_inst, &ff_front, &ff_proj})
       b->release();
     view = uw::MeshDev<T>();
     ready = false;
@@ -337,6 +352,12 @@ uw_status ensure_tables(Engine& E) {
   up(d.t_eta, convert<T>(S.t_eta));
   up(d.fnb, S.fnb);
   if (!S.inflow.empty()) up(d.inflow, S.inflow);
+  if (!S.ff_front.empty()) {
+    up(d.fronts, S.fronts);
+    up(d.front_inst, S.front_inst);
+    up(d.ff_front, S.ff_front);
+    up(d.ff_proj, S.ff_proj);
+  }
   {
     std::vector<T> nrm;
     std::vector<double> coef;
@@ -371,6 +392,12 @@ uw_status ensure_tables(Engine& E) {
   v.tri.eta = d.t_eta.template as<T>();
   v.fnb = d.fnb.template as<int32_t>();
   v.inflow = S.inflow.empty() ? nullptr : d.inflow.template as<double>();
+  // fronts is the kernels' test for front faces: null when there are none
+  const bool ff = !S.ff_front.empty();
+  v.fronts = ff ? d.fronts.template as<double>() : nullptr;
+  v.front_inst = ff ? d.front_inst.template as<int32_t>() : nullptr;
+  v.ff_front = ff ? d.ff_front.template as<int32_t>() : nullptr;
+  v.ff_proj = ff ? d.ff_proj.template as<double>() : nullptr;
   v.special = S.special;
   v.fnrm = d.fnrm.template as<T>();
   v.fcoef = d.fcoef.template as<double>();
@@ -425,14 +452,15 @@ hipError_t ev_begin(Engine& E, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
 // One residual evaluation (mode 0) or RK stage (modes 1..3).
 template <class T>
 uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, const double* Wn,
-                double* W_out, hipStream_t st, bool timed) {
+                double* W_out, const uw::StageTime& tm, hipStream_t st, bool timed) {
   const int nvar = nvar_of(p);
   DevTables<T>& d = tables_of<T>(E);
   T* FS = E.FS.template as<T>();
   const bool prof = timed && E.profiling;
   hipEvent_t a = nullptr, b = nullptr;
   if (prof) UW_HIP(ev_begin(E, st, &a, &b));
-  hipError_t e = uw::launch_recon<T>(d.view, E.scheme, phys_dev(p), E.sched, nvar, W_in, FS, st);
+  hipError_t e =
+      uw::launch_recon<T>(d.view, E.scheme, phys_dev(p), E.sched, nvar, W_in, FS, tm, st);
   if (e != hipSuccess) return hip_fail(e, "reconstruction launch");
   if (prof) {
     UW_HIP(hipEventRecord(b, st));
@@ -440,7 +468,7 @@ uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, co
     UW_HIP(ev_begin(E, st, &a, &b));
   }
   e = uw::launch_flux<T>(d.view, phys_dev(p), E.sched, nvar, mode, FS, W_in, Wn, W_out,
-                         E.dt.as<double>(), E.flag.as<int>(), st);
+                         E.dt.as<double>(), E.flag.as<int>(), tm, st);
   if (e != hipSuccess) return hip_fail(e, "flux launch");
   if (prof) {
     UW_HIP(hipEventRecord(b, st));
@@ -464,9 +492,11 @@ uw_status rk3(Engine& E, const uw_physics* p, double* W, double cfl, double dt_f
                                    t_dev, E.partial.as<double>(), E.dt.as<double>(), st);
   if (e != hipSuccess) return hip_fail(e, "time-step launch");
   double* W1 = E.Wtmp.as<double>();
-  UW_TRY(stage<T>(E, p, 1, W, W, W1, st, timed));
-  UW_TRY(stage<T>(E, p, 2, W1, W, W1, st, timed));
-  UW_TRY(stage<T>(E, p, 3, W1, W, W, st, timed));
+  // the stages see the boundary data at t, t + dt and t + dt/2
+  const double* dtp = E.dt.as<double>();
+  UW_TRY(stage<T>(E, p, 1, W, W, W1, uw::StageTime{t_dev, dtp, 0.0, 0.0}, st, timed));
+  UW_TRY(stage<T>(E, p, 2, W1, W, W1, uw::StageTime{t_dev, dtp, 1.0, 0.0}, st, timed));
+  UW_TRY(stage<T>(E, p, 3, W1, W, W, uw::StageTime{t_dev, dtp, 0.5, 0.0}, st, timed));
   e = uw::launch_advance(E.staged.n_inst, t_dev, E.dt.as<double>(), st);
   if (e != hipSuccess) return hip_fail(e, "time advance launch");
   return UW_OK;
@@ -571,8 +601,13 @@ uw_status uw_mesh_upload(const uw_mesh_desc* desc, int device, uw_mesh** out) {
   if (desc->bc != UW_BC_PERIODIC && desc->bc != UW_BC_TRANSMISSIVE)
     return fail(UW_EINVAL, "bc must be UW_BC_PERIODIC or UW_BC_TRANSMISSIVE");
   if (desc->n_cells > (int64_t(1) << 28)) return fail(UW_EINVAL, "at most 2^28 cells");
-  if (desc->n_inflow < 0 || desc->n_inflow > (1 << 20) || (desc->n_inflow > 0 && !desc->inflow_W))
-    return fail(UW_EINVAL, "n_inflow must be in [0, 2^20] with inflow_W given");
+  if (desc->n_inflow < 0 || desc->n_inflow > UW_BC_FRONT - UW_BC_INFLOW ||
+      (desc->n_inflow > 0 && !desc->inflow_W))
+    return fail(UW_EINVAL, "n_inflow must be in [0, 65533] with inflow_W given");
+  if (desc->n_fronts < 0 || desc->n_fronts > (1 << 20) || (desc->n_fronts > 0 && !desc->fronts))
+    return fail(UW_EINVAL, "n_fronts must be in [0, 2^20] with fronts given");
+  for (int64_t q = 0; q < 12 * (int64_t)desc->n_fronts; ++q)
+    if (!std::isfinite(desc->fronts[q])) return fail(UW_EINVAL, "fronts must be finite");
   uw_mesh* m = new (std::nothrow) uw_mesh();
   if (!m) return fail(UW_ENOMEM, "host allocation");
   m->eng.device = device;
@@ -580,7 +615,7 @@ uw_status uw_mesh_upload(const uw_mesh_desc* desc, int device, uw_mesh** out) {
   try {
     if (!uw::build_mesh(desc->n_nodes, desc->node_xy, desc->n_cells, desc->cell_nodes,
                         desc->node_id, desc->bc, desc->face_bc, desc->n_inflow, desc->inflow_W,
-                        m->host, err)) {
+                        desc->n_fronts, desc->fronts, m->host, err)) {
       delete m;
       return fail((uw_status)err.code, err.msg);
     }
@@ -692,18 +727,25 @@ uw_status uw_mesh_table(const uw_mesh* m, int32_t which, double* out) {
   return UW_OK;
 }
 
-uw_status uw_residual(uw_mesh* m, const uw_physics* p, const double* W, double* L, void* stream) {
+uw_status uw_residual_at(uw_mesh* m, const uw_physics* p, const double* W, double* L, double t,
+                         void* stream) {
   g_err.clear();
   if (!m || !W || !L) return fail(UW_EINVAL, "mesh, W and L must not be NULL");
+  if (!std::isfinite(t)) return fail(UW_EINVAL, "t must be finite");
   UW_TRY(check_physics(p));
   UW_TRY(mesh_ready(m));
   hipStream_t st = (hipStream_t)stream;
+  const uw::StageTime tm{nullptr, nullptr, 0.0, t};
   if (p->precision == UW_FP64) {
     UW_TRY(prepare<double>(m->eng, p));
-    return stage<double>(m->eng, p, 0, W, W, L, st, true);
+    return stage<double>(m->eng, p, 0, W, W, L, tm, st, true);
   }
   UW_TRY(prepare<float>(m->eng, p));
-  return stage<float>(m->eng, p, 0, W, W, L, st, true);
+  return stage<float>(m->eng, p, 0, W, W, L, tm, st, true);
+}
+
+uw_status uw_residual(uw_mesh* m, const uw_physics* p, const double* W, double* L, void* stream) {
+  return uw_residual_at(m, p, W, L, 0.0, stream);
 }
 
 uw_status uw_rk3_step(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,
@@ -751,7 +793,7 @@ uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* p
   UW_TRY(check_physics(p));
   std::vector<const uw::HostMesh*> hm;
   std::vector<const uw::HostTables*> ht;
-  int64_t total = 0;
+  int64_t total = 0, states = 0, ffaces = 0;
   for (int32_t k = 0; k < n; ++k) {
     uw_mesh* m = meshes[k];
     if (!m || !m->precomputed) return fail(UW_ESTATE, "every batch mesh must be precomputed");
@@ -764,8 +806,14 @@ uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* p
     hm.push_back(&m->host);
     ht.push_back(&m->tables);
     total += m->host.N;
+    states += (int64_t)m->host.inflow.size() / 4;
+    ffaces += (int64_t)m->host.ff_face.size();
   }
   if (total > (int64_t(1) << 28)) return fail(UW_EINVAL, "at most 2^28 cells in a batch");
+  // boundary codes: -3 - s for state s must stay above the front codes
+  if (states > -uw::kFrontCode - 4)
+    return fail(UW_EINVAL, "at most 2^24 - 4 prescribed states in a batch");
+  if (ffaces > (int64_t(1) << 30)) return fail(UW_EINVAL, "at most 2^30 front faces in a batch");
   uw_batch* b = new (std::nothrow) uw_batch();
   if (!b) return fail(UW_ENOMEM, "host allocation");
   b->physics = *p;
@@ -882,10 +930,10 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
         hipError_t e = hipEventRecord(e0, st);
         if (e == hipSuccess) {
           s = p->precision == UW_FP64
-                  ? stage<double>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(), st,
-                                  false)
-                  : stage<float>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(), st,
-                                 false);
+                  ? stage<double>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(),
+                                  uw::StageTime{}, st, false)
+                  : stage<float>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(),
+                                 uw::StageTime{}, st, false);
           if (s == UW_OK) e = hipEventRecord(e1, st);
           if (s == UW_OK && e == hipSuccess) e = hipEventSynchronize(e1);
           float ms = 0.0f;

@@ -116,13 +116,29 @@ __device__ inline int stage_tile(const double* __restrict__ W, int64_t N, const 
   return len;
 }
 
-// State outside a boundary face of kind -pk (pk < 0) with outward unit
-// normal (nx, ny), from the inner state w: -1 transmissive (w itself), -2
-// slip wall (w with its normal momentum reversed; transmissive for a scalar),
-// -3 - s prescribed state s.
-template <typename U, int V>
-__device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny,
-                                     const double* __restrict__ inflow, U* g) {
+// Time at which instance `inst` sees its boundary data.
+__device__ inline double stage_time(const StageTime& tm, int inst) {
+  double t = tm.t ? tm.t[inst] : tm.t0;
+  if (tm.dt) t = t + tm.c * tm.dt[inst];   // c dt is exact for c = 0, 1, 1/2
+  return t;
+}
+
+// Position c0 + s t of a moving front, rounded as two separate operations.
+__device__ inline double front_position(double c0, double s, double t) {
+#pragma clang fp contract(off)
+  return c0 + s * t;
+}
+
+// State outside a boundary face with code pk < 0 and outward unit normal
+// (nx, ny), from the inner state w: -1 transmissive (w itself), -2 slip
+// wall (w with its normal momentum reversed; transmissive for a scalar),
+// -3 - s prescribed state s, kFrontCode - j front face j (state A of its
+// front where the face lies behind the front's position at the stage time
+// of the front's instance, else state B; everything is looked up here, so
+// that the common faces keep no extra registers live).
+template <typename U, int V, typename T>
+__device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny, const MeshDev<T>& m,
+                                     U* g) {
 #pragma unroll
   for (int v = 0; v < V; ++v) g[v] = w[v];
   if (pk == -2) {
@@ -131,16 +147,24 @@ __device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny,
       g[1] = w[1] - U(2) * mn * nx;
       g[2] = w[2] - U(2) * mn * ny;
     }
+  } else if (pk <= kFrontCode) {
+    const int32_t j = kFrontCode - pk;
+    const int32_t fi = m.ff_front[j];
+    const double* f = m.fronts + 12 * fi;
+    const double tnow = stage_time(m.tm, m.front_inst[fi]);
+    const double* st = f + (m.ff_proj[j] < front_position(f[2], f[3], tnow) ? 4 : 8);
+#pragma unroll
+    for (int v = 0; v < V; ++v) g[v] = (U)st[v];
   } else if (pk <= -3) {
-    const double* st = inflow + 4 * (-3 - pk);
+    const double* st = m.inflow + 4 * (-3 - pk);
 #pragma unroll
     for (int v = 0; v < V; ++v) g[v] = (U)st[v];
   }
 }
 
-// Ghost face neighbours of a wall or inflow face carry that face's outside
-// state (a transmissive ghost reads the cell itself, as staged): replace
-// the difference of slot k + 1, the neighbour across face k.
+// Ghost face neighbours of a wall, inflow or front face carry that face's
+// outside state (a transmissive ghost reads the cell itself, as staged):
+// replace the difference of slot k + 1, the neighbour across face k.
 template <typename T, int NF, int V>
 __device__ inline void ghost_differences(const MeshDev<T>& m, int64_t i, const double* w0,
                                          T (&dW)[Layout<NF>::S - 1][V]) {
@@ -151,7 +175,7 @@ __device__ inline void ghost_differences(const MeshDev<T>& m, int64_t i, const d
     if (pk <= -2) {
       double g[V];
       outside_state<double, V>(pk, w0, (double)m.fnrm[(k * 2 + 0) * m.N + i],
-                               (double)m.fnrm[(k * 2 + 1) * m.N + i], m.inflow, g);
+                               (double)m.fnrm[(k * 2 + 1) * m.N + i], m, g);
 #pragma unroll
       for (int v = 0; v < V; ++v) dW[k][v] = (T)(g[v] - w0[v]);
     }
@@ -375,7 +399,7 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
     if (pk <= -2) {
       // a wall or inflow face: its outside state is the ghost neighbour
       double g[V];
-      outside_state<double, V>(pk, w0, (double)nxk, (double)nyk, m.inflow, g);
+      outside_state<double, V>(pk, w0, (double)nxk, (double)nyk, m, g);
 #pragma unroll
       for (int v = 0; v < V; ++v) Wk[v] = (T)g[v];
     } else {
@@ -649,8 +673,8 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
       bool left = true;
       if (pk < 0) {
         // boundary face: the outside states (the stored normal is the cell's)
-        outside_state<T, V>(pk, o0, nx, ny, m.inflow, t0);
-        outside_state<T, V>(pk, o1, nx, ny, m.inflow, t1);
+        outside_state<T, V>(pk, o0, nx, ny, m, t0);
+        outside_state<T, V>(pk, o1, nx, ny, m, t1);
       } else {
         const int64_t c = pk >> 3;
         const int kp = (pk >> 1) & 3;
@@ -808,8 +832,11 @@ size_t lds_limit() {
 }
 
 template <typename T>
-hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& p,
-                        const Schedule& sch, int nvar, const double* W, T* FS, hipStream_t st) {
+hipError_t launch_recon(const MeshDev<T>& m0, const SchemeDev& s, const PhysDev& p,
+                        const Schedule& sch, int nvar, const double* W, T* FS,
+                        const StageTime& tm, hipStream_t st) {
+  MeshDev<T> m = m0;
+  m.tm = tm;
   const int kind = s.mode == 1 ? 1 : (s.vars == 1 && nvar == 4 ? 2 : 0);
   const T eps = (T)s.eps, th = (T)s.theta, gam = (T)p.gamma;
   auto one = [&](int ntiles, int maxlen, int want, auto nf_tag) -> hipError_t {
@@ -840,9 +867,11 @@ hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& 
 }
 
 template <typename T>
-hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, const Schedule& sch, int nvar,
+hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& sch, int nvar,
                        int mode, const T* FS, const double* W_in, const double* Wn, double* W_out,
-                       const double* dt, int* flag, hipStream_t st) {
+                       const double* dt, int* flag, const StageTime& tm, hipStream_t st) {
+  MeshDev<T> m = m0;
+  m.tm = tm;
   const int ntiles = m.n_tq + m.n_tt;
   if (ntiles <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
@@ -891,15 +920,17 @@ hipError_t launch_advance(int n_inst, double* t, const double* dt, hipStream_t s
 
 template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, const PhysDev&,
                                          const Schedule&, int, const double*, double*,
-                                         hipStream_t);
+                                         const StageTime&, hipStream_t);
 template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&, const PhysDev&,
-                                        const Schedule&, int, const double*, float*, hipStream_t);
+                                        const Schedule&, int, const double*, float*,
+                                        const StageTime&, hipStream_t);
 template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, const Schedule&,
                                         int, int, const double*, const double*, const double*,
-                                        double*, const double*, int*, hipStream_t);
+                                        double*, const double*, int*, const StageTime&,
+                                        hipStream_t);
 template hipError_t launch_flux<float>(const MeshDev<float>&, const PhysDev&, const Schedule&, int,
                                        int, const float*, const double*, const double*, double*,
-                                       const double*, int*, hipStream_t);
+                                       const double*, int*, const StageTime&, hipStream_t);
 template hipError_t launch_cfl<double>(const MeshDev<double>&, const PhysDev&, int, const double*,
                                        double, double, double, const double*, double*, double*,
                                        hipStream_t);

@@ -104,13 +104,15 @@ static double shoelace(const double* xy, const int32_t* c, int nf) {
 
 bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_t* cells,
                 const int32_t* node_id, int bc, const int32_t* face_bc, int32_t n_inflow,
-                const double* inflow_W, HostMesh& m, Error& err) {
+                const double* inflow_W, int32_t n_fronts, const double* fronts, HostMesh& m,
+                Error& err) {
   const int threads = default_threads();
   m.n_nodes = n_nodes;
   m.N = n_cells;
   m.periodic = (bc == 0);
   m.xy.assign(xy, xy + 2 * n_nodes);
   m.inflow.assign(inflow_W ? inflow_W : xy, inflow_W ? inflow_W + 4 * (int64_t)n_inflow : xy);
+  m.fronts.assign(fronts ? fronts : xy, fronts ? fronts + 12 * (int64_t)n_fronts : xy);
 
   // ---- validation
   std::vector<int32_t> nf0(n_cells);
@@ -219,8 +221,9 @@ bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_
         err = {2, "unmatched face on a periodic mesh"};
         return false;
       }
-      if (kind < 0 || kind > 2 + n_inflow) {
-        err = {1, "face_bc: unknown kind or prescribed state index"};
+      const bool front = kind >= kFrontKind && kind - kFrontKind < n_fronts;
+      if (kind < 0 || (kind > 2 + n_inflow && !front)) {
+        err = {1, "face_bc: unknown kind, prescribed state or front index"};
         return false;
       }
       bkind0[4 * c + k] = kind;
@@ -293,6 +296,25 @@ bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_
       }
     }
   });
+  // faces on moving fronts: the side of the front is decided on e.m, m the
+  // midpoint of the face's two nodes as given
+  m.ff_face.clear();
+  m.ff_front.clear();
+  m.ff_proj.clear();
+  for (int64_t i = 0; i < n_cells; ++i)
+    for (int k = 0; k < m.nf[i]; ++k) {
+      const int32_t kind = m.bkind[4 * i + k];
+      if (kind < kFrontKind) continue;
+      const int32_t f = kind - kFrontKind;
+      const int32_t a = m.cell_nodes[4 * i + k], b = m.cell_nodes[4 * i + (k + 1) % m.nf[i]];
+      const double mx = 0.5 * (xy[2 * a] + xy[2 * b]);
+      const double my = 0.5 * (xy[2 * a + 1] + xy[2 * b + 1]);
+      const double px = m.fronts[12 * f] * mx;
+      const double py = m.fronts[12 * f + 1] * my;
+      m.ff_face.push_back((int32_t)(4 * i + k));
+      m.ff_front.push_back(f);
+      m.ff_proj.push_back(px + py);
+    }
 
   // ---- stencils (Sec. 3.1 / 3.2 selection procedures)
   m.st_cell.assign(kMaxS * n_cells, -1);

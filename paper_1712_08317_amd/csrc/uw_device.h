@@ -32,6 +32,19 @@ struct TypeDev {
   const T* eta = nullptr;           // [2n*(S-1)][Nt] point-value coefficients (linear mode)
 };
 
+// Boundary codes of face tables (fnb): -1 transmissive, -2 reflective,
+// -3 - s prescribed state s, kFrontCode - j front face j.
+constexpr int32_t kFrontCode = -(1 << 24);
+
+// Time at which an evaluation sees its boundary data: t[inst] (or t0 when
+// t is null) plus c dt[inst] (none when dt is null).  The stages of a
+// Runge-Kutta step from t take c = 0, 1 and 1/2.
+struct StageTime {
+  const double* t = nullptr;
+  const double* dt = nullptr;
+  double c = 0.0, t0 = 0.0;
+};
+
 template <typename T>
 struct MeshDev {
   int64_t N = 0;                    // cells of all instances
@@ -44,9 +57,14 @@ struct MeshDev {
   const int32_t* inst_tiles = nullptr; // [2][n_inst + 1] quad / triangle tile ranges per instance
   TypeDev<T> quad, tri;
   const int32_t* fnb = nullptr;     // [4][N] (nbr << 3) | (nbr_face << 1) | left; boundary:
-                                    // -1 transmissive, -2 reflective, -3 - s prescribed state s
+                                    // the codes above
   const double* inflow = nullptr;   // [n_states][4] prescribed states (conserved)
-  int32_t special = 0;              // 1 if any face is a wall or takes a prescribed state
+  const double* fronts = nullptr;   // [n_fronts][12] (ex, ey, c0, s, A[4], B[4])
+  const int32_t* front_inst = nullptr; // [n_fronts] instance of each front
+  const int32_t* ff_front = nullptr;   // [n_front_faces] front of each front face
+  const double* ff_proj = nullptr;     // [n_front_faces] e.m of its midpoint m
+  int32_t special = 0;              // 1 if any face is a wall, prescribed state or front
+  StageTime tm;                     // set per launch
   const T* fnrm = nullptr;          // [4*2][N] canonical unit normal of each face
   const double* fcoef = nullptr;    // [4][N] |l| / (2 |Omega_i|), closed for the stored normals
 };
@@ -71,14 +89,15 @@ struct Schedule {
 // Face states at the Gauss points: FS[(i*8 + g)*V + v].
 template <typename T>
 hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& p,
-                        const Schedule& sch, int nvar, const double* W, T* FS, hipStream_t st);
+                        const Schedule& sch, int nvar, const double* W, T* FS,
+                        const StageTime& tm, hipStream_t st);
 
 // Flux, residual gather and RK stage.  mode 0: W_out = L(W_in); mode 1..3:
 // the three stages of the TVD Runge-Kutta scheme from W_in, Wn and dt[inst].
 template <typename T>
 hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, const Schedule& sch, int nvar,
                        int mode, const T* FS, const double* W_in, const double* Wn, double* W_out,
-                       const double* dt, int* flag, hipStream_t st);
+                       const double* dt, int* flag, const StageTime& tm, hipStream_t st);
 
 // Per instance k: dt[k] = min(cfl * min_i 1 / sum_p coef_p (|u.n_p| + c),
 // t_end - t[k]) (or min(dt_fixed, t_end - t[k]) if dt_fixed > 0); t may be

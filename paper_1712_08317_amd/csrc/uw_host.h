@@ -30,6 +30,10 @@ inline const TypeConst& type_const(int nf) { return nf == 4 ? kQuad : kTri; }
 constexpr int kMaxS = 13, kMaxM = 12, kMaxG = 8;
 constexpr int kTile = 256;   // cells per reconstruction block
 
+// face kind of the first moving front (kinds 3 .. kFrontKind - 1 are
+// prescribed states)
+constexpr int32_t kFrontKind = 1 << 16;
+
 struct Error {
   int code;
   std::string msg;
@@ -49,9 +53,15 @@ struct HostMesh {
   std::vector<double> shift;         // [N*4*2]
   std::vector<uint8_t> left;         // [N*4] 1: this cell is the canonical left state
   // boundary kind of each unmatched face: 1 transmissive, 2 reflective,
-  // 3 + s prescribed state s; 0 for matched and unused faces
+  // 3 + s prescribed state s, kFrontKind + f moving front f; 0 for matched
+  // and unused faces
   std::vector<int32_t> bkind;        // [N*4]
   std::vector<double> inflow;        // [n_inflow*4] prescribed conserved states
+  std::vector<double> fronts;        // [n_fronts*12] (ex, ey, c0, s, A[4], B[4])
+  // faces on moving fronts, by internal cell and face: 4*i + k, the front,
+  // and e.m of the face midpoint m (FP64, no fused multiply-add)
+  std::vector<int32_t> ff_face, ff_front;
+  std::vector<double> ff_proj;
   // stencils
   std::vector<int32_t> st_cell;      // [N*13] slot cell (ghost: self; absent: -1)
   std::vector<double> st_shift;      // [N*13*2]
@@ -65,7 +75,8 @@ struct HostMesh {
 // err on an invalid mesh.
 bool build_mesh(int64_t n_nodes, const double* xy, int64_t n_cells, const int32_t* cells,
                 const int32_t* node_id, int bc, const int32_t* face_bc, int32_t n_inflow,
-                const double* inflow_W, HostMesh& m, Error& err);
+                const double* inflow_W, int32_t n_fronts, const double* fronts, HostMesh& m,
+                Error& err);
 
 struct SchemeParams {
   double zeta = 1e-14, theta = 3.0, eps = 1e-3;
