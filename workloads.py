@@ -495,14 +495,16 @@ def shock_vortex(n: int = 100, jitter: float = 0.3, seed: int = 12, split="tri",
 
 
 def double_mach(nx: int = 400, ny: int = 100, split="tri", jitter: float = 0.15, seed: int = 13,
-                gamma=GAMMA):
+                gamma=GAMMA, t: float = 0.0):
     """Double Mach reflection (Sec. 4.4): [0,4] x [0,1], a Mach 10 shock
     through (1/6, 0) at 60 degrees to the x-axis, post-shock state
     (8, 4.125 sqrt3, -4.125, 116.5) behind it and (1.4, 0, 0, 1) ahead.  The
     bottom is a slip wall from x = 1/6 on and carries the post-shock state
     before it, the left end takes the post-shock state, the right end is
     open, and the top follows the exact shock: post-shock where
-    x < 1/6 + (1 + 20 t)/sqrt3, else pre-shock.  Returns (mesh, state)."""
+    x < 1/6 + (1 + 20 t)/sqrt3, else pre-shock.  The state is the incident
+    shock alone at time t (the exact solution at t = 0; later, away from the
+    reflection that forms at the wall).  Returns (mesh, state)."""
     post = np.asarray(primitive_to_conserved(8.0, 4.125 * math.sqrt(3.0), -4.125, 116.5, gamma))
     pre = np.asarray(primitive_to_conserved(1.4, 0.0, 0.0, 1.0, gamma))
     mesh = grid_mesh(nx, ny, 4.0, 1.0, split, jitter, seed, False, name=f"dmr{nx}x{ny}")
@@ -521,7 +523,7 @@ def double_mach(nx: int = 400, ny: int = 100, split="tri", jitter: float = 0.15,
     mesh.inflow = post[None, :].copy()
     mesh.fronts = np.concatenate([[1.0, 0.0, x0 + 1.0 / r3, 20.0 / r3], post, pre])[None, :]
     cx, cy = cell_centres(mesh)
-    behind = cx < x0 + cy / r3
+    behind = cx < x0 + (cy + 20.0 * t) / r3
     W = np.where(behind[None, :], post[:, None], pre[:, None])
     return mesh, W
 
