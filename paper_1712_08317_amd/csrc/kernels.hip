@@ -135,8 +135,9 @@ __device__ inline double front_position(double c0, double s, double t) {
 // -3 - s prescribed state s, kFrontCode - j front face j (state A of its
 // front where the face lies behind the front's position at the stage time
 // of the front's instance, else state B; everything is looked up here, so
-// that the common faces keep no extra registers live).
-template <typename U, int V, typename T>
+// that the common faces keep no extra registers live).  FRONTS = false
+// compiles the front case out, for meshes without front faces.
+template <typename U, int V, typename T, bool FRONTS = true>
 __device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny, const MeshDev<T>& m,
                                      U* g) {
 #pragma unroll
@@ -147,7 +148,7 @@ __device__ inline void outside_state(int32_t pk, const U* w, U nx, U ny, const M
       g[1] = w[1] - U(2) * mn * nx;
       g[2] = w[2] - U(2) * mn * ny;
     }
-  } else if (pk <= kFrontCode) {
+  } else if (FRONTS && pk <= kFrontCode) {
     const int32_t j = kFrontCode - pk;
     const int32_t fi = m.ff_front[j];
     const double* f = m.fronts + 12 * fi;
@@ -646,7 +647,11 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
   }
 }
 
-template <typename T, int V, int MODE>
+// FRONTS: the mesh has moving-front faces.  Measured on gfx950: the flux
+// kernel runs 8% slower on meshes without such faces when the front case is
+// compiled in, although it never executes, so it has an instantiation
+// without it.
+template <typename T, int V, int MODE, bool FRONTS>
 __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
                                                      const T* __restrict__ FS, const double* W_in,
                                                      const double* Wn, double* W_out,
@@ -673,8 +678,8 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
       bool left = true;
       if (pk < 0) {
         // boundary face: the outside states (the stored normal is the cell's)
-        outside_state<T, V>(pk, o0, nx, ny, m, t0);
-        outside_state<T, V>(pk, o1, nx, ny, m, t1);
+        outside_state<T, V, T, FRONTS>(pk, o0, nx, ny, m, t0);
+        outside_state<T, V, T, FRONTS>(pk, o1, nx, ny, m, t1);
       } else {
         const int64_t c = pk >> 3;
         const int kp = (pk >> 1) & 3;
@@ -875,8 +880,13 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
   const int ntiles = m.n_tq + m.n_tt;
   if (ntiles <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
-#define UW_FLUX(V, MODE) \
-  k_flux<T, V, MODE><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag)
+#define UW_FLUX(V, MODE)                                                                    \
+  do {                                                                                      \
+    if (m.fronts)                                                                           \
+      k_flux<T, V, MODE, true><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag); \
+    else                                                                                    \
+      k_flux<T, V, MODE, false><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag); \
+  } while (0)
   if (nvar == 4) {
     switch (mode) {
       case 0: UW_FLUX(4, 0); break;
