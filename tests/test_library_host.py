@@ -167,3 +167,23 @@ def test_boundary_kinds_are_validated(uw):
     # the stencils do not depend on the kinds
     M2 = uw.Mesh(mesh.node_xy, mesh.cell_nodes, None, uw.UW_BC_TRANSMISSIVE, device=-1)
     assert all(np.array_equal(a, b) for a, b in zip(M.export(), M2.export()))
+
+
+def test_front_kinds_are_validated(uw):
+    mesh, _ = wl.double_mach(nx=8, ny=2)
+    # accepted as built
+    uw.Mesh.from_workload(mesh, device=-1)
+    args = (mesh.node_xy, mesh.cell_nodes, None, uw.UW_BC_TRANSMISSIVE)
+    # a front index past the list
+    bad = np.where(mesh.face_bc >= uw.UW_BC_FRONT, uw.UW_BC_FRONT + 1, mesh.face_bc)
+    for kw in (dict(face_bc=bad, inflow=mesh.inflow, fronts=mesh.fronts),
+               dict(face_bc=mesh.face_bc, inflow=mesh.inflow),               # no fronts at all
+               dict(face_bc=mesh.face_bc, inflow=mesh.inflow,
+                    fronts=np.where(np.arange(12) == 5, np.nan, mesh.fronts)),   # not finite
+               dict(face_bc=mesh.face_bc, inflow=np.ones((65534, 4)), fronts=mesh.fronts)):
+        with pytest.raises(uw.UwError) as e:
+            uw.Mesh(*args, device=-1, **kw)
+        assert e.value.status == uw.UW_EINVAL, kw.keys()
+    # prescribed states up to the front kinds are accepted
+    uw.Mesh(*args, device=-1, face_bc=mesh.face_bc, inflow=np.ones((65533, 4)),
+            fronts=mesh.fronts)
