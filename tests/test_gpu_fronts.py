@@ -52,7 +52,7 @@ def _crossing_time(mesh, after):
     return times[np.searchsorted(times, after, side="right")]
 
 
-@pytest.mark.parametrize("split", ["tri", "quad"])
+@pytest.mark.parametrize("split", ["tri", "quad", "lattice"])
 @pytest.mark.parametrize("scheme", list(SCHEMES))
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_front_residual_matches_oracle_at_given_times(split, scheme, prec):
@@ -92,7 +92,7 @@ def _oracle_steps(T, W, t0, dt, steps):
     return ref
 
 
-@pytest.mark.parametrize("split,steps", [("tri", 1), ("quad", 3)])
+@pytest.mark.parametrize("split,steps", [("tri", 1), ("quad", 3), ("lattice", 3)])
 def test_front_rk3_steps_see_the_stage_times(split, steps):
     """Steps in characteristic variables from a time chosen so that the
     shock reaches a top-face midpoint three quarters into the first step: its

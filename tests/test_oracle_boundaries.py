@@ -202,3 +202,22 @@ def test_wall_reconstruction_does_not_follow_rounding():
     a = _wall_states(mesh, W1, cells, t0 + dt)
     b = _wall_states(moved, W1, cells, t0 + dt)
     assert np.abs(a - b).max() <= 1e-9 * np.abs(a).max()
+
+
+def test_lattice_mesh_is_near_equilateral():
+    """The lattice generator: positive areas that sum to the domain, interior
+    triangles with three equal sides (rows sqrt3/2 apart), and every
+    boundary face on the box."""
+    import math
+    nx = 20
+    ny = int(round(nx / 4.0 / (math.sqrt(3) / 2)))
+    mesh = wl.lattice_mesh(nx, ny, 4.0, 1.0)
+    a = wl.signed_areas(mesh.node_xy, mesh.cell_nodes)
+    assert (a > 0).all() and abs(a.sum() - 4.0) < 1e-12
+    xy = mesh.node_xy[mesh.cell_nodes[:, :3]]
+    sides = np.linalg.norm(xy - np.roll(xy, -1, axis=1), axis=2)
+    inner = (xy[:, :, 0].min(1) > 0.0) & (xy[:, :, 0].max(1) < 4.0)
+    assert inner.sum() > 0.8 * mesh.n_cells
+    spread = (sides.max(1) - sides.min(1)) / sides.max(1)
+    # rows are 1/ny apart, within 4% of sqrt3/2 h for this nx
+    assert spread[inner].max() < 0.05

@@ -11,7 +11,8 @@ Meshes
 All meshes are structured-derived: an ``nx`` by ``ny`` grid of squares of
 side ``h`` whose interior nodes are moved by a seeded uniform jitter, each
 square kept as one counter-clockwise quadrilateral or split into two
-counter-clockwise triangles along its (i,j)-(i+1,j+1) diagonal.  The paper's
+counter-clockwise triangles along its (i,j)-(i+1,j+1) diagonal; or
+(``lattice_mesh``) rows of near-equilateral triangles.  The paper's
 own test meshes (the "regular" and "irregular" families of its accuracy
 section) exist only as figures; these jittered grids stand in for them.
 
@@ -494,6 +495,36 @@ def shock_vortex(n: int = 100, jitter: float = 0.3, seed: int = 12, split="tri",
     return mesh, cell_averages(mesh, f, 4, q=3)
 
 
+def lattice_mesh(nx: int, ny: int, lx: float, ly: float, name: str = "") -> Mesh:
+    """Near-equilateral triangles on [0,lx] x [0,ly]: ny + 1 rows of nodes,
+    odd rows shifted by half the spacing lx/nx (their end nodes kept on
+    x = 0 and x = lx), each strip between two rows zipped into triangles
+    from left to right.  With ny = ly/(lx/nx)/(sqrt3/2) the interior
+    triangles are equilateral."""
+    hx = lx / nx
+    rows, xy = [], []
+    for j in range(ny + 1):
+        y = ly * j / ny
+        xs = ([i * hx for i in range(nx + 1)] if j % 2 == 0
+              else [0.0] + [(i + 0.5) * hx for i in range(nx)] + [lx])
+        rows.append(list(range(len(xy), len(xy) + len(xs))))
+        xy += [(x, y) for x in xs]
+    xy = np.array(xy, dtype=np.float64)
+    cells = []
+    for j in range(ny):
+        b, top = rows[j], rows[j + 1]
+        ib = it = 0
+        while ib < len(b) - 1 or it < len(top) - 1:
+            if it == len(top) - 1 or (ib < len(b) - 1 and xy[b[ib + 1], 0] <= xy[top[it + 1], 0]):
+                cells.append((b[ib], b[ib + 1], top[it], -1))
+                ib += 1
+            else:
+                cells.append((b[ib], top[it + 1], top[it], -1))
+                it += 1
+    return Mesh(node_xy=xy, cell_nodes=np.array(cells, dtype=np.int32), node_id=None,
+                period=(0.0, 0.0), bc="transmissive", h=hx, name=name or f"lattice{nx}x{ny}")
+
+
 def double_mach(nx: int = 400, ny: int = 100, split="tri", jitter: float = 0.15, seed: int = 13,
                 gamma=GAMMA, t: float = 0.0):
     """Double Mach reflection (Sec. 4.4): [0,4] x [0,1], a Mach 10 shock
@@ -504,10 +535,16 @@ def double_mach(nx: int = 400, ny: int = 100, split="tri", jitter: float = 0.15,
     open, and the top follows the exact shock: post-shock where
     x < 1/6 + (1 + 20 t)/sqrt3, else pre-shock.  The state is the incident
     shock alone at time t (the exact solution at t = 0; later, away from the
-    reflection that forms at the wall).  Returns (mesh, state)."""
+    reflection that forms at the wall).  split "quad" or "tri" (squares,
+    split along a diagonal, jittered) or "lattice" (near-equilateral
+    triangles of side 4/nx, ny ignored).  Returns (mesh, state)."""
     post = np.asarray(primitive_to_conserved(8.0, 4.125 * math.sqrt(3.0), -4.125, 116.5, gamma))
     pre = np.asarray(primitive_to_conserved(1.4, 0.0, 0.0, 1.0, gamma))
-    mesh = grid_mesh(nx, ny, 4.0, 1.0, split, jitter, seed, False, name=f"dmr{nx}x{ny}")
+    if split == "lattice":
+        rows = int(round(nx / 4.0 / (math.sqrt(3.0) / 2.0)))
+        mesh = lattice_mesh(nx, rows, 4.0, 1.0, name=f"dmr-lattice{nx}x{rows}")
+    else:
+        mesh = grid_mesh(nx, ny, 4.0, 1.0, split, jitter, seed, False, name=f"dmr{nx}x{ny}")
     x0, r3 = 1.0 / 6.0, math.sqrt(3.0)
     tol = 1e-9
 
