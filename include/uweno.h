@@ -222,7 +222,11 @@ uw_status uw_cfl_dt(uw_mesh* mesh, const uw_physics* physics, const double* W, d
  * their tables (the meshes may be destroyed afterwards).
  * Batch state: device FP64 [V][N_total], N_total = sum of the instances'
  * cells; instance k occupies cells [cell_offsets[k], cell_offsets[k+1]) in
- * its own internal order. */
+ * its own internal order.  Prescribed states and moving fronts stay with
+ * their instance (each instance's fronts see its own time t_dev[k]).
+ * Errors: UW_ESTATE (a mesh not precomputed), UW_EINVAL (meshes on
+ * different devices or with different schemes, more than 2^28 cells, more
+ * than 2^24 - 4 prescribed states or 2^30 front faces in total). */
 uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* physics,
                           uw_batch** out);
 /* cell_offsets: host [n+1]. */
