@@ -880,29 +880,26 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
   const int ntiles = m.n_tq + m.n_tt;
   if (ntiles <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
-#define UW_FLUX(V, MODE)                                                                    \
-  do {                                                                                      \
-    if (m.fronts)                                                                           \
-      k_flux<T, V, MODE, true><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag); \
-    else                                                                                    \
-      k_flux<T, V, MODE, false><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag); \
-  } while (0)
-  if (nvar == 4) {
+  // meshes without front faces get the instantiation without the front case
+  auto go = [&](auto v_tag, auto mode_tag) {
+    constexpr int V = decltype(v_tag)::value, MD = decltype(mode_tag)::value;
+    if (m.fronts)
+      k_flux<T, V, MD, true><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+    else
+      k_flux<T, V, MD, false><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+  };
+  auto by_mode = [&](auto v_tag) {
     switch (mode) {
-      case 0: UW_FLUX(4, 0); break;
-      case 1: UW_FLUX(4, 1); break;
-      case 2: UW_FLUX(4, 2); break;
-      default: UW_FLUX(4, 3); break;
+      case 0: go(v_tag, std::integral_constant<int, 0>{}); break;
+      case 1: go(v_tag, std::integral_constant<int, 1>{}); break;
+      case 2: go(v_tag, std::integral_constant<int, 2>{}); break;
+      default: go(v_tag, std::integral_constant<int, 3>{}); break;
     }
-  } else {
-    switch (mode) {
-      case 0: UW_FLUX(1, 0); break;
-      case 1: UW_FLUX(1, 1); break;
-      case 2: UW_FLUX(1, 2); break;
-      default: UW_FLUX(1, 3); break;
-    }
-  }
-#undef UW_FLUX
+  };
+  if (nvar == 4)
+    by_mode(std::integral_constant<int, 4>{});
+  else
+    by_mode(std::integral_constant<int, 1>{});
   return hipGetLastError();
 }
 
