@@ -29,7 +29,8 @@ uw_status fail(uw_status s, const std::string& msg) {
 }
 
 uw_status hip_fail(hipError_t e, const char* what) {
-  return fail(UW_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+  return fail(e == hipErrorOutOfMemory ? UW_ENOMEM : UW_EDEVICE,
+              std::string(what) + ": " + hipGetErrorString(e));
 }
 
 #define UW_HIP(call)                                  \
