@@ -108,7 +108,8 @@ typedef struct {
 } uw_mesh_desc;
 
 /* Scheme constants (paper Sec. 3): zeta of eq. (quadratic-2) (1e-14), theta
- * of the weight split of Sec. 3.4 (3), eps of the nonlinear weights (not
+ * of the weight split of Sec. 3.4 (3; it must exceed 1: at 1 the negative
+ * part of an all-positive weight set is empty), eps of the nonlinear weights (not
  * given by the paper; 1e-3), optimize = apply the linear-weight optimisation
  * of Sec. 3.3 (1), d_scope = UW_D_PER_GP (weights d from each Gauss point's
  * own linear weights) or UW_D_PER_CELL, mode = UW_WENO or UW_LINEAR (the
@@ -116,7 +117,8 @@ typedef struct {
  * UW_CONSERVED (component-wise) or UW_CHARACTERISTIC (Euler only; Sec. 4:
  * WENO on the characteristic variables of Roe's mean matrix between the
  * cell and the neighbour across each face, projected back; ignored for
- * scalar advection and in UW_LINEAR mode).  Any other value: UW_EINVAL. */
+ * scalar advection and in UW_LINEAR mode).  Any other value: UW_EINVAL.
+ * theta is built into the tables by uw_precompute_geometry. */
 typedef struct {
   double zeta, theta, eps;
   int32_t optimize, d_scope, mode, variables;

@@ -145,7 +145,7 @@ struct Staged {
   int32_t special = 0;          // any wall, prescribed-state or front face
   int64_t rows_q = 0, rows_t = 0;
   std::vector<uint16_t> q_lidx, t_lidx;
-  std::vector<double> q_Y, q_off, q_gam, q_eta, t_Y, t_off, t_gam, t_eta, fgeo;
+  std::vector<double> q_Y, q_off, q_gam, q_sig, q_eta, t_Y, t_off, t_gam, t_sig, t_eta, fgeo;
 };
 
 template <class V, class Get>
@@ -224,6 +224,8 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
              ro, q ? S.q_off : S.t_off);
     cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.gam; }, R,
              ro, q ? S.q_gam : S.t_gam);
+    cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.sig; }, R,
+             ro, q ? S.q_sig : S.t_sig);
     if (linear)
       cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.eta; },
                R, ro, q ? S.q_eta : S.t_eta);
@@ -263,12 +265,12 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
 template <class T>
 struct DevTables {
   bool ready = false;
-  DevBuf tiles, tile_off, tile_ids, inst_tiles, q_li, q_Y, q_off, q_gam, q_eta, t_li, t_Y, t_off,
-      t_gam, t_eta, fnb, fnrm, fcoef, inflow, fronts, front_inst, ff_front, ff_proj;
+  DevBuf tiles, tile_off, tile_ids, inst_tiles, q_li, q_Y, q_off, q_gam, q_sig, q_eta, t_li, t_Y,
+      t_off, t_gam, t_sig, t_eta, fnb, fnrm, fcoef, inflow, fronts, front_inst, ff_front, ff_proj;
   uw::MeshDev<T> view;
   void reset() {
     for (DevBuf* b : {&tiles, &tile_off, &tile_ids, &inst_tiles, &q_li, &q_Y, &q_off, &q_gam,
-                      &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_eta, &fnb, &fnrm, &fcoef,
+                      &q_sig, &q_eta, &t_li, &t_Y, &t_off, &t_gam, &t_sig, &t_eta, &fnb, &fnrm, &fcoef,
                       &inflow, &fronts, &front_inst, &ff_front, &ff_proj})
       b->release();
     view = uw::MeshDev<T>();
@@ -345,11 +347,13 @@ uw_status ensure_tables(Engine& E) {
   up(d.q_Y, convert<T>(S.q_Y));
   up(d.q_off, convert<T>(S.q_off));
   up(d.q_gam, convert<T>(S.q_gam));
+  up(d.q_sig, convert<T>(S.q_sig));
   up(d.q_eta, convert<T>(S.q_eta));
   up(d.t_li, S.t_lidx);
   up(d.t_Y, convert<T>(S.t_Y));
   up(d.t_off, convert<T>(S.t_off));
   up(d.t_gam, convert<T>(S.t_gam));
+  up(d.t_sig, convert<T>(S.t_sig));
   up(d.t_eta, convert<T>(S.t_eta));
   up(d.fnb, S.fnb);
   if (!S.inflow.empty()) up(d.inflow, S.inflow);
@@ -384,12 +388,14 @@ uw_status ensure_tables(Engine& E) {
   v.quad.Y = d.q_Y.template as<T>();
   v.quad.off = d.q_off.template as<T>();
   v.quad.gam = d.q_gam.template as<T>();
+  v.quad.sig = d.q_sig.template as<T>();
   v.quad.eta = d.q_eta.template as<T>();
   v.tri.Nt = S.rows_t;
   v.tri.lidx = d.t_li.template as<uint16_t>();
   v.tri.Y = d.t_Y.template as<T>();
   v.tri.off = d.t_off.template as<T>();
   v.tri.gam = d.t_gam.template as<T>();
+  v.tri.sig = d.t_sig.template as<T>();
   v.tri.eta = d.t_eta.template as<T>();
   v.fnb = d.fnb.template as<int32_t>();
   v.inflow = S.inflow.empty() ? nullptr : d.inflow.template as<double>();
@@ -543,8 +549,8 @@ uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, doubl
 
 uw_status check_scheme(const uw_scheme* sc) {
   if (!sc) return fail(UW_EINVAL, "scheme is NULL");
-  if (!(sc->zeta >= 0.0) || !(sc->eps > 0.0) || !(sc->theta >= 1.0))
-    return fail(UW_EINVAL, "scheme needs zeta >= 0, eps > 0, theta >= 1");
+  if (!(sc->zeta >= 0.0) || !(sc->eps > 0.0) || !(sc->theta > 1.0) || !std::isfinite(sc->theta))
+    return fail(UW_EINVAL, "scheme needs zeta >= 0, eps > 0, theta > 1");
   if (sc->mode != UW_WENO && sc->mode != UW_LINEAR) return fail(UW_EINVAL, "scheme.mode");
   if (sc->variables != UW_CONSERVED && sc->variables != UW_CHARACTERISTIC)
     return fail(UW_EINVAL, "scheme.variables");

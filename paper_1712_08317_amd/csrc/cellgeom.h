@@ -68,7 +68,8 @@ struct CellIn {
 struct TypeOut {
   double* Y;     // [M*4][n]
   double* off;   // [2n*2][n]
-  double* gam;   // [2n*M][n]
+  double* gam;   // [2n*M][n] gamma_j / (2 sigma+) per Gauss point (split form)
+  double* sig;   // [2n*3][n] sigma+, sigma-, sigma+ / sigma- per Gauss point
   double* eta;   // [2n*(S-1)][n] or null
   int32_t* sid;  // [S-1][n]
   int64_t n;
@@ -90,7 +91,7 @@ struct CellOut {
 };
 
 struct Params {
-  double zeta;
+  double zeta, theta;
   int optimize, d_scope, linear;
 };
 
@@ -454,7 +455,19 @@ UW_HD inline void precompute_cell(const CellIn& in, const TypeC& TQ, const TypeC
     // outputs of this Gauss point
     to.off[(2 * g) * nrow + r] = pG[g][0];
     to.off[(2 * g + 1) * nrow + r] = pG[g][1];
-    for (int j = 0; j < M; ++j) to.gam[(g * M + j) * nrow + r] = gam[j];
+    // the split of Sec. 3.4 in the form the reconstruction uses: with
+    // h_j = gamma_j / (2 sigma+), the normalised weights are
+    // gamma+_j = h_j + theta |h_j| and gamma-_j = (sigma+/sigma-)(gamma+_j - 2 h_j)
+    double sgp = 0.0, sgm = 0.0;
+    for (int j = 0; j < M; ++j) {
+      const double tp = 0.5 * (gam[j] + sp.theta * fabs(gam[j]));
+      sgp += tp;
+      sgm += tp - gam[j];
+    }
+    for (int j = 0; j < M; ++j) to.gam[(g * M + j) * nrow + r] = gam[j] / (2.0 * sgp);
+    to.sig[(3 * g) * nrow + r] = sgp;
+    to.sig[(3 * g + 1) * nrow + r] = sgm;
+    to.sig[(3 * g + 2) * nrow + r] = sgp / sgm;
     if (to.eta)
       for (int q = 1; q < S; ++q) to.eta[(g * (S - 1) + q - 1) * nrow + r] = eta[q];
     if (out.dbg_gamma) {

@@ -211,6 +211,20 @@ __device__ inline void weno_load(const TypeDev<T>& td, int64_t r, WenoIn<T, NF>&
     for (int k = 0; k < 4; ++k) in.Y[j][k] = td.Y[(j * 4 + k) * n + r];
 }
 
+// Normalised split weights of one Gauss point (Sec. 3.4) from the stored
+// h_j = gamma_j / (2 sigma+) and sigma+/sigma-: gamma~+_j = (gamma_j +
+// theta |gamma_j|)/2 gives gamma+_j = gamma~+_j / sigma+ = h_j + theta |h_j|,
+// and gamma~-_j = gamma~+_j - gamma_j gives gamma-_j = (sigma+/sigma-)
+// (gamma+_j - 2 h_j).
+template <typename T, int M>
+__device__ inline void split_weights(const T (&h)[M], T theta, T ratio, T (&gp)[M], T (&gm)[M]) {
+#pragma unroll
+  for (int j = 0; j < M; ++j) {
+    gp[j] = fma(theta, fabs(h[j]), h[j]);
+    gm[j] = ratio * fma(T(-2), h[j], gp[j]);
+  }
+}
+
 // WENO point values of one cell at its 2n Gauss points (paper Sec. 3.4).
 template <typename T, int NF, int V>
 __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
@@ -220,10 +234,13 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
   constexpr int S = L::S, M = L::M, G = 2 * NF;
   const int64_t n = td.Nt;
   // the first Gauss point's weights and offsets (prefetching kernel)
-  T ga_n[M], ox_n = 0, oy_n = 0;
+  T ga_n[M], ox_n = 0, oy_n = 0, s0_n = 0, s1_n = 0, s2_n = 0;
   if (kPrefetch<NF>) {
     ox_n = td.off[r];
     oy_n = td.off[n + r];
+    s0_n = td.sig[r];
+    s1_n = td.sig[n + r];
+    s2_n = td.sig[2 * n + r];
 #pragma unroll
     for (int j = 0; j < M; ++j) ga_n[j] = td.gam[j * n + r];
   }
@@ -259,43 +276,35 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
   }
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
-    T ox, oy, ga[M];
+    T ox, oy, ga[M], sp, sm, ratio;
     if (kPrefetch<NF>) {
       ox = ox_n;
       oy = oy_n;
+      sp = s0_n;
+      sm = s1_n;
+      ratio = s2_n;
 #pragma unroll
       for (int j = 0; j < M; ++j) ga[j] = ga_n[j];
       if (g + 1 < G) {
         ox_n = td.off[(2 * g + 2) * n + r];
         oy_n = td.off[(2 * g + 3) * n + r];
+        s0_n = td.sig[(3 * g + 3) * n + r];
+        s1_n = td.sig[(3 * g + 4) * n + r];
+        s2_n = td.sig[(3 * g + 5) * n + r];
 #pragma unroll
         for (int j = 0; j < M; ++j) ga_n[j] = td.gam[((g + 1) * M + j) * n + r];
       }
     } else {
       ox = td.off[(2 * g) * n + r];
       oy = td.off[(2 * g + 1) * n + r];
+      sp = td.sig[(3 * g) * n + r];
+      sm = td.sig[(3 * g + 1) * n + r];
+      ratio = td.sig[(3 * g + 2) * n + r];
 #pragma unroll
       for (int j = 0; j < M; ++j) ga[j] = td.gam[(g * M + j) * n + r];
     }
-    // split of the linear weights: gamma~+ = (gamma + theta|gamma|)/2,
-    // gamma~- = gamma~+ - gamma, normalised by their sums sigma+-
     T gp[M], gm[M];
-    T sp = 0, sm = 0;
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      const T tp = T(0.5) * (ga[j] + theta * fabs(ga[j]));
-      const T tm = tp - ga[j];
-      gp[j] = tp;
-      gm[j] = tm;
-      sp += tp;
-      sm += tm;
-    }
-    const T rp = rcp(sp), rm = rcp(sm);
-#pragma unroll
-    for (int j = 0; j < M; ++j) {
-      gp[j] *= rp;
-      gm[j] *= rm;
-    }
+    split_weights<T, M>(ga, theta, ratio, gp, gm);
     T R[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
@@ -419,23 +428,12 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
       const int g = 2 * k + q;
       ox[q] = td.off[(2 * g) * n + r];
       oy[q] = td.off[(2 * g + 1) * n + r];
-      sp[q] = 0;
-      sm[q] = 0;
+      sp[q] = td.sig[(3 * g) * n + r];
+      sm[q] = td.sig[(3 * g + 1) * n + r];
+      T h[M];
 #pragma unroll
-      for (int j = 0; j < M; ++j) {
-        const T ga = td.gam[(g * M + j) * n + r];
-        const T tp = T(0.5) * (ga + theta * fabs(ga));
-        gp[q][j] = tp;
-        gm[q][j] = tp - ga;
-        sp[q] += tp;
-        sm[q] += tp - ga;
-      }
-      const T rp = rcp(sp[q]), rm = rcp(sm[q]);
-#pragma unroll
-      for (int j = 0; j < M; ++j) {
-        gp[q][j] *= rp;
-        gm[q][j] *= rm;
-      }
+      for (int j = 0; j < M; ++j) h[j] = td.gam[(g * M + j) * n + r];
+      split_weights<T, M>(h, theta, td.sig[(3 * g + 2) * n + r], gp[q], gm[q]);
     }
     T inc[2][V];   // reconstructed increments per field at the two points
 #pragma unroll

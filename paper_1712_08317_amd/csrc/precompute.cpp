@@ -44,6 +44,7 @@ void alloc_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t) {
     tt->Y.assign(T.M * 4 * n, 0.0);
     tt->off.assign(2 * T.n * 2 * n, 0.0);
     tt->gam.assign(2 * T.n * T.M * n, 0.0);
+    tt->sig.assign(2 * T.n * 3 * n, 0.0);
     tt->eta.assign(linear ? 2 * T.n * (T.S - 1) * n : 0, 0.0);
   }
   t.area.assign(N, 0.0);
@@ -83,9 +84,9 @@ void precompute_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t,
                   m.st_res.data(),   m.st_present.data(), m.Nq};
   geom::CellOut out;
   out.quad = geom::TypeOut{t.quad.Y.data(), t.quad.off.data(), t.quad.gam.data(),
-                           t.quad.eta.empty() ? nullptr : t.quad.eta.data(), t.quad.sid.data(),
-                           t.quad.Nt};
-  out.tri = geom::TypeOut{t.tri.Y.data(), t.tri.off.data(), t.tri.gam.data(),
+                           t.quad.sig.data(), t.quad.eta.empty() ? nullptr : t.quad.eta.data(),
+                           t.quad.sid.data(), t.quad.Nt};
+  out.tri = geom::TypeOut{t.tri.Y.data(), t.tri.off.data(), t.tri.gam.data(), t.tri.sig.data(),
                           t.tri.eta.empty() ? nullptr : t.tri.eta.data(), t.tri.sid.data(),
                           t.tri.Nt};
   out.area = t.area.data();
@@ -99,7 +100,7 @@ void precompute_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t,
   out.dbg_Y = t.debug ? t.dbg_Y.data() : nullptr;
   out.dbg_off = t.debug ? t.dbg_off.data() : nullptr;
   const geom::TypeC tq = type_c(kQuad), tt = type_c(kTri);
-  const geom::Params gp{sp.zeta, sp.optimize, sp.d_scope, sp.mode == 1};
+  const geom::Params gp{sp.zeta, sp.theta, sp.optimize, sp.d_scope, sp.mode == 1};
   parallel_for(N, threads, [&](int64_t s, int64_t e) {
     for (int64_t i = s; i < e; ++i) geom::precompute_cell(in, tq, tt, gp, i, out);
   });

@@ -79,6 +79,7 @@ bool precompute_tables_device(const HostMesh& m, const SchemeParams& sp, HostTab
     o.Y = out_of(tt.Y);
     o.off = out_of(tt.off);
     o.gam = out_of(tt.gam);
+    o.sig = out_of(tt.sig);
     o.eta = out_of(tt.eta);
     o.sid = out_of(tt.sid);
     o.n = tt.Nt;
@@ -98,7 +99,7 @@ bool precompute_tables_device(const HostMesh& m, const SchemeParams& sp, HostTab
   out.dbg_off = t.debug ? out_of(t.dbg_off) : nullptr;
   if (e == hipSuccess && N > 0) {
     const geom::TypeC tq = type_c(kQuad), tt = type_c(kTri);
-    const geom::Params gp{sp.zeta, sp.optimize, sp.d_scope, sp.mode == 1};
+    const geom::Params gp{sp.zeta, sp.theta, sp.optimize, sp.d_scope, sp.mode == 1};
     k_precompute<<<(unsigned)((N + 63) / 64), 64>>>(in, tq, tt, gp, out, N);
     e = hipGetLastError();
     if (e == hipSuccess) e = hipDeviceSynchronize();

@@ -28,7 +28,8 @@ struct TypeDev {
   const uint16_t* lidx = nullptr;   // [S][Nt] LDS position of each stencil slot (0 = the cell)
   const T* Y = nullptr;             // [M*4][Nt] candidate operators
   const T* off = nullptr;           // [2n*2][Nt] Gauss-point offsets (p^1, p^2)
-  const T* gam = nullptr;           // [2n*M][Nt] optimised linear weights
+  const T* gam = nullptr;           // [2n*M][Nt] optimised linear weights / (2 sigma+)
+  const T* sig = nullptr;           // [2n*3][Nt] sigma+, sigma-, sigma+/sigma- of the split
   const T* eta = nullptr;           // [2n*(S-1)][Nt] point-value coefficients (linear mode)
 };
 

@@ -96,7 +96,8 @@ struct TypeTables {
   int32_t max_tile_len = 0;
   std::vector<double> Y;        // [M*4][Nt] candidate operators (Y00, Y01, Y10, Y11)
   std::vector<double> off;      // [2n*2][Nt] (p^1, p^2) at each Gauss point
-  std::vector<double> gam;      // [2n*M][Nt] optimised linear weights
+  std::vector<double> gam;      // [2n*M][Nt] optimised linear weights / (2 sigma+)
+  std::vector<double> sig;      // [2n*3][Nt] sigma+, sigma-, sigma+/sigma- of the split
   std::vector<double> eta;      // [2n*(S-1)][Nt] point-value coefficients of P^2 (linear mode)
 };
 

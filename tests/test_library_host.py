@@ -187,3 +187,14 @@ def test_front_kinds_are_validated(uw):
     # prescribed states up to the front kinds are accepted
     uw.Mesh(*args, device=-1, face_bc=mesh.face_bc, inflow=np.ones((65533, 4)),
             fronts=mesh.fronts)
+
+
+def test_split_parameter_must_exceed_one(uw):
+    """theta = 1 leaves the negative part of an all-positive weight set
+    empty (0/0 in its normalisation): rejected."""
+    mesh = wl.grid_mesh(6, 6, 1.0, 1.0, "quad", 0.1, 1, True)
+    M = uw.Mesh.from_workload(mesh, device=-1)
+    with pytest.raises(uw.UwError) as e:
+        M.precompute(uw.make_scheme(theta=1.0))
+    assert e.value.status == uw.UW_EINVAL
+    M.precompute(uw.make_scheme(theta=1.5))
