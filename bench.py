@@ -39,15 +39,16 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-# Algorithmic bytes of the reconstruction kernel per cell (the tables as the
-# kernel reads them): stencil indices 4(S-1), Gauss-point offsets 4n,
-# candidate operators 4M, linear weights in split form 2nM and the split sums
-# sigma+, sigma-, sigma+/sigma- 6n values of p bytes, and the cell's own state
-# V * 8 bytes.  Face states written for the flux kernel
+# Algorithmic bytes of the reconstruction kernel per cell (minimal table
+# representation, one linear weight per Gauss point and candidate): stencil
+# indices 4(S-1), Gauss-point offsets 4n, candidate operators 4M and linear
+# weights 2nM values of p bytes, and the cell's own state V * 8 bytes.  The
+# split sums the kernel also reads (3 per Gauss point) and the face states it
+# writes for the flux kernel are implementation traffic and are not counted.  Face states written for the flux kernel
 # are implementation traffic and are not counted.
 def recon_bytes(nf, p, nvar):
     S, M = (13, 12) if nf == 4 else (10, 9)
-    return 4 * (S - 1) + p * (4 * nf + 4 * M + 2 * nf * M + 6 * nf) + nvar * 8
+    return 4 * (S - 1) + p * (4 * nf + 4 * M + 2 * nf * M) + nvar * 8
 
 
 # Whole cell-stage (both kernels): recon bytes plus the face table (3n
@@ -61,10 +62,11 @@ def stage_bytes(nf, p, nvar):
 # formulas of Sec. 3.4 (an add, multiply or division is one flop, a fused
 # multiply-add two, |.| none): differences to the stencil cells (S-1)V;
 # candidate gradients Y_j dW (6) and beta_j = |g_j|^2 (3) per (j, v); per
-# Gauss point and candidate the normalised split weights from the stored
-# h_j = gamma_j / (2 sigma+) and sigma+/sigma- (gamma+ = h + theta|h|: 2,
-# gamma- = (sigma+/sigma-)(gamma+ - 2h): 3; the sums sigma+- depend on the
-# mesh only and are precomputed); per (Gauss point, j, v) the candidate value
+# Gauss point and candidate the split gamma~+- = ((gamma + theta|gamma|)/2,
+# gamma~+ - gamma) (4), their sums (2) and normalisation (2), plus the two
+# reciprocals of sigma+- (the kernel takes the sums, which depend on the mesh
+# only, from the precompute and does less); per (Gauss point, j, v) the
+# candidate value
 # d = ox gx + oy gy (3) and, for each sign, t = gamma~ beta (1), 1 + t + t^2
 # (3), beta (.) + eps (2), its square (1), alpha = gamma~ / (.)^2 (1),
 # sum alpha d (2), sum alpha (1); per (Gauss point, v) the two ratios (2),
@@ -78,7 +80,7 @@ def recon_flops(nf, nvar, characteristic=False):
     S, M = (13, 12) if nf == 4 else (10, 9)
     G = 2 * nf
     per_sign = 1 + 3 + 2 + 1 + 1 + 2 + 1
-    common = G * 5 * M + G * M * nvar * (3 + 2 * per_sign) + G * nvar * 6
+    common = G * (8 * M + 2) + G * M * nvar * (3 + 2 * per_sign) + G * nvar * 6
     if characteristic and nvar == 4:
         return ((S - 1) * nvar + common + nf * (80 + nvar * ((S - 1) * 7 + 10 * M))
                 + G * nvar * 8)
