@@ -4,6 +4,19 @@ Argument marshalling only: every step of the per-stage operator runs in the
 HIP kernels of ``libuweno.so``.  PyTorch supplies device memory and streams.
 The library must have been built (``python paper_1712_08317_amd/build.py``);
 importing this module raises if it is missing.
+
+Typical use (state ``W`` as cell averages [V, n] in the mesh's own order)::
+
+    import torch, paper_1712_08317_amd as uw
+    M = uw.Mesh(node_xy, cell_nodes, bc=uw.UW_BC_TRANSMISSIVE)   # renumbered
+    M.precompute(uw.make_scheme(variables=uw.UW_CHARACTERISTIC))
+    ph = uw.make_physics(uw.UW_EULER, precision=uw.UW_FP32)
+    Wd = torch.from_numpy(M.to_internal(W)).cuda()
+    t = torch.zeros(1, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        M.rk3_step(ph, Wd, t, cfl=0.5, t_end=t_end)
+    M.check()                                   # raises on NaN or rho, p <= 0
+    W = M.to_original(Wd.cpu().numpy())
 """
 from __future__ import annotations
 
