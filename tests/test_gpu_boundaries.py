@@ -189,3 +189,18 @@ def test_nonpositive_pressure_is_flagged():
     with pytest.raises(uw.UwError) as e:
         M.check()
     assert e.value.status == uw.UW_ENONFINITE
+
+
+@pytest.mark.parametrize("mesh_name", ["box-inflow", "channel-tri", "channel-quad"])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_scalar_advection_with_boundary_faces(mesh_name, prec):
+    """Scalar advection u_t + u_x + u_y = 0 on meshes with prescribed-state,
+    wall and open faces: the prescribed value is the first component of the
+    state, a wall is open for a scalar."""
+    uw, mesh, M, T = _setup(mesh_name, "conserved")
+    W = wl.seeded_state(mesh, 1, 97, amp=0.05)
+    ref = osc.residual_vectorized(T, W, osc.Physics("advection", 1.0, 1.0))
+    got = gpu_residual(uw, M, W, "advection", prec)
+    err = rel_l1(got, ref)
+    print(mesh_name, prec, "advection rel L1", err)
+    assert err <= (1e-12 if prec == "fp64" else 1e-5)
