@@ -198,3 +198,20 @@ def test_split_parameter_must_exceed_one(uw):
         M.precompute(uw.make_scheme(theta=1.0))
     assert e.value.status == uw.UW_EINVAL
     M.precompute(uw.make_scheme(theta=1.5))
+
+
+def test_c_abi_from_plain_c(uw, tmp_path):
+    """include/uweno.h compiles as C99 and a C program linked against the
+    library uploads, precomputes and inspects a host-only mesh."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    exe = tmp_path / "c_abi_check"
+    libdir = os.path.dirname(uw.LIB_PATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    os.path.join(ROOT, "tests", "c_abi_check.c"), "-o", str(exe), "-L", libdir,
+                    "-luweno", "-Wl,-rpath," + libdir], check=True)
+    r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0 and r.stdout.strip().endswith("ok"), r.stdout + r.stderr
