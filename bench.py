@@ -144,23 +144,34 @@ def cpu_baseline(seconds_hint=20.0):
     import workloads as wl
     from oracle import weights as ow
     from oracle import scheme as osc
+    import contextlib
+    try:
+        from threadpoolctl import threadpool_limits
+        one_thread = threadpool_limits(1)     # NumPy's BLAS and OpenMP pools
+    except ImportError:
+        one_thread = contextlib.nullcontext()
     mesh = wl.mesh_c5(n=128, block=64, jitter=0.30, seed=6)
     T = ow.precompute(mesh)
     W = wl.initial_state("c5", mesh)
     ph = osc.Physics("euler")
     dt = osc.cfl_dt(T, W, ph, 0.5)
-    t0 = time.perf_counter()
-    steps = 0
-    while True:
-        W = osc.rk3_step(T, W, ph, dt)
-        steps += 1
-        el = time.perf_counter() - t0
-        if el > seconds_hint or steps >= 50:
-            break
+    with one_thread:
+        c0 = os.times()
+        t0 = time.perf_counter()
+        steps = 0
+        while True:
+            W = osc.rk3_step(T, W, ph, dt)
+            steps += 1
+            el = time.perf_counter() - t0
+            if el > seconds_hint or steps >= 50:
+                break
+        c1 = os.times()
+    busy = (c1.user - c0.user + c1.system - c0.system) / el   # CPU seconds per second
     rate = mesh.n_cells * 3 * steps / el
     return {"value": rate, "unit": "cell-stage updates/s", "cores": 1, "kind": "oracle",
             "sample": f"oracle rk3 on a {mesh.n_cells}-cell mixed mesh (128x128 squares, "
-                      f"64x64 checkerboard, 30% jitter), {steps} steps, {el:.1f} s, single thread"}
+                      f"64x64 checkerboard, 30% jitter), {steps} steps, {el:.1f} s, one thread "
+                      f"(thread pools limited to 1; {busy:.2f} CPU-s per s measured)"}
 
 
 def run_batch(args):
