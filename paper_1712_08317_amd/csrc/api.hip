@@ -293,7 +293,9 @@ struct Engine {
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
   // captured multi-step graphs, keyed by their arguments
-  std::map<std::tuple<const void*, const void*, int, double, double, double, int>, hipGraphExec_t>
+  std::map<std::tuple<const void*, const void*, int, double, double, double, int, double, double,
+                      double>,
+           hipGraphExec_t>
       graphs;
   // graphs cannot be captured on the null stream: calls made on it capture
   // and replay on this blocking stream, which orders itself with the null one
@@ -415,10 +417,22 @@ uw_status ensure_tables(Engine& E) {
 uw_status ensure_work(Engine& E, int nvar, size_t fs_elem) {
   const int64_t N = E.staged.N;
   const int64_t ntiles = (int64_t)E.staged.n_tq + E.staged.n_tt;
-  UW_HIP(E.FS.ensure((size_t)N * 8 * nvar * fs_elem));
-  UW_HIP(E.Wtmp.ensure((size_t)N * nvar * sizeof(double)));
+  const size_t fs_bytes = (size_t)N * 8 * nvar * fs_elem;
+  const size_t w_bytes = (size_t)N * nvar * sizeof(double);
+  // a buffer about to be replaced may still be read by queued launches or
+  // graphs: let the device finish first
+  if ((E.FS.p && fs_bytes > E.FS.bytes) || (E.Wtmp.p && w_bytes > E.Wtmp.bytes))
+    UW_HIP(hipDeviceSynchronize());
+  const void* before[4] = {E.FS.p, E.Wtmp.p, E.dt.p, E.partial.p};
+  UW_HIP(E.FS.ensure(fs_bytes));
+  UW_HIP(E.Wtmp.ensure(w_bytes));
   UW_HIP(E.dt.ensure((size_t)E.staged.n_inst * sizeof(double)));
   UW_HIP(E.partial.ensure((size_t)std::max<int64_t>(ntiles, 1) * sizeof(double)));
+  // captured graphs hold the work buffers' addresses: a buffer that moved
+  // (a larger one for more variables or a wider precision) retires them
+  const void* after[4] = {E.FS.p, E.Wtmp.p, E.dt.p, E.partial.p};
+  for (int k = 0; k < 4; ++k)
+    if (before[k] && before[k] != after[k]) E.clear_graphs();
   if (!E.flag.p) {
     UW_HIP(E.flag.ensure(sizeof(int)));
     UW_HIP(hipMemset(E.flag.p, 0, sizeof(int)));
@@ -523,7 +537,7 @@ uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, doubl
     st = E.own_stream;
   }
   auto key = std::make_tuple((const void*)W, (const void*)t_dev, n_steps, cfl, dt_fixed, t_end,
-                             p->precision * 16 + p->equation);
+                             p->precision * 16 + p->equation, p->gamma, p->ax, p->ay);
   auto it = E.graphs.find(key);
   if (it == E.graphs.end()) {
     UW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));

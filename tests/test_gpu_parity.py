@@ -269,3 +269,39 @@ def test_single_mesh_graph_replays_match_eager_steps():
             assert torch.equal(Wg, We), (prec, rep)
             assert tg.item() == te.item()
         M.check()
+
+
+def test_graphs_follow_physics_and_moved_work_buffers():
+    """A captured step is tied to its physics (gamma, advection velocity)
+    and to the library's work buffers: a call with other physics on the
+    same state captures anew, and a call that needs larger buffers (Euler
+    after scalar advection) retires the graphs that held the old ones.
+    Each graph result is checked against eager launches."""
+    import torch
+    import paper_1712_08317_amd as uw
+    mesh = wl.grid_mesh(16, 16, 2.0, 2.0, "tri", 0.2, 21, True)
+
+    def run(graph, seq):
+        M = uw.Mesh.from_workload(mesh, device=0)
+        M.precompute()
+        M.profile(enable=0 if graph else 1)
+        Wa = torch.from_numpy(M.to_internal(wl.seeded_state(mesh, 1, 22))).to("cuda:0")
+        We = torch.from_numpy(M.to_internal(wl.seeded_state(mesh, 4, 23))).to("cuda:0")
+        ta = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        te = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        for what, gamma, ax in seq:
+            if what == "adv":
+                M.rk3_step(uw.make_physics(uw.UW_ADVECTION, ax, 1.0, 1.4, uw.UW_FP64), Wa, ta,
+                           dt_fixed=0.01)
+            else:
+                M.rk3_step(uw.make_physics(uw.UW_EULER, 1.0, 1.0, gamma, uw.UW_FP64), We, te,
+                           dt_fixed=0.005)
+        torch.cuda.synchronize()
+        M.check()
+        return Wa.cpu(), We.cpu()
+
+    seq = [("adv", 1.4, 1.0), ("euler", 1.4, 1.0), ("adv", 1.4, 1.0), ("adv", 1.4, -0.5),
+           ("euler", 1.67, 1.0), ("euler", 1.4, 1.0)]
+    ga, ge = run(True, seq)
+    ea, ee = run(False, seq)
+    assert torch.equal(ga, ea) and torch.equal(ge, ee)
