@@ -176,7 +176,9 @@ uw_status uw_mesh_export(const uw_mesh* mesh, int32_t* slots, uint8_t* present, 
  * (linearweight-matrix), the optimisation of Sec. 3.3.  Runs on the mesh's
  * GPU (one thread per cell) or, for a host-only mesh, on host threads, with
  * the same per-cell code.  The per-precision device tables are uploaded on
- * first use.  `diag` is nullable.
+ * first use; a repeated call first waits for the device to finish the work
+ * queued with the old tables, and drops the captured steps.  `diag` is
+ * nullable.
  * Errors: UW_ESTATE (mesh not uploaded), UW_EINVAL, UW_ENOMEM, UW_EDEVICE. */
 uw_status uw_precompute_geometry(uw_mesh* mesh, const uw_scheme* scheme, uw_diag* diag);
 
@@ -269,6 +271,8 @@ uw_status uw_profile(uw_mesh* mesh, int32_t enable, double* ms, int64_t* count);
  * batch (UW_ENONFINITE), clearing it. */
 uw_status uw_check(uw_mesh* mesh, uw_batch* batch, void* stream);
 
+/* Free a mesh or batch and everything it holds on the device, after the
+ * device has finished the work queued on it.  NULL is ignored. */
 void uw_mesh_destroy(uw_mesh* mesh);
 void uw_batch_destroy(uw_batch* batch);
 

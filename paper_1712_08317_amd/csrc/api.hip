@@ -310,6 +310,11 @@ struct Engine {
     graphs.clear();
   }
   ~Engine() {
+    // queued launches and graphs may still use the buffers freed below
+    if (device >= 0 && (d64.ready || d32.ready || FS.p)) {
+      (void)hipSetDevice(device);
+      (void)hipDeviceSynchronize();
+    }
     clear_graphs();
     if (own_stream) (void)hipStreamDestroy(own_stream);
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
@@ -695,6 +700,11 @@ uw_status uw_precompute_geometry(uw_mesh* m, const uw_scheme* sc, uw_diag* diag)
   m->scheme.optimize = sc->optimize;
   m->scheme.d_scope = sc->d_scope;
   m->scheme.mode = sc->mode;
+  // queued launches and graphs may still read the tables about to be freed
+  if (m->eng.device >= 0 && (m->eng.d64.ready || m->eng.d32.ready)) {
+    UW_HIP(hipSetDevice(m->eng.device));
+    UW_HIP(hipDeviceSynchronize());
+  }
   m->eng.reset_device();
   m->eng.staged = Staged();
   m->eng.staged_ready = false;
