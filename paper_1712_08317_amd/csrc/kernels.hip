@@ -184,14 +184,21 @@ __device__ inline void ghost_differences(const MeshDev<T>& m, int64_t i, const d
 }
 
 // Per-cell inputs of the WENO reconstruction that do not depend on the
-// state.  Latency hiding (measured on gfx950): the triangle kernel reads them
-// before the tile's staging barrier, so that their latency overlaps the
-// staging loads, and fetches each Gauss point's weights one point ahead;
-// the quadrilateral kernel, whose candidate state already fills the
-// registers of two waves per SIMD, reads them when needed (the extra live
-// registers would halve its occupancy, which costs more than it saves).
+// state.  Latency hiding (measured on gfx950): the triangle kernel reads the
+// stencil positions and candidate operators before the tile's staging
+// barrier, so that their latency overlaps the staging loads; the
+// quadrilateral kernel, whose candidate state already fills the registers of
+// two waves per SIMD, reads them when needed (held across the barrier they
+// spill about 270 bytes per lane).
 template <int NF>
 constexpr bool kPrefetch = NF == 3;
+
+// Each Gauss point's offsets and weights are fetched one point ahead by the
+// triangle kernels and by the FP32 quadrilateral kernel (there at the cost
+// of a 24-byte spill per lane, 4% faster than reading them when needed); the
+// FP64 quadrilateral kernel reads them when needed (ahead they spill).
+template <typename T, int NF>
+constexpr bool kPrefetchGP = NF == 3 || sizeof(T) == 4;
 
 template <typename T, int NF>
 struct WenoIn {
@@ -235,7 +242,7 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
   const int64_t n = td.Nt;
   // the first Gauss point's weights and offsets (prefetching kernel)
   T ga_n[M], ox_n = 0, oy_n = 0, s0_n = 0, s1_n = 0, s2_n = 0;
-  if (kPrefetch<NF>) {
+  if (kPrefetchGP<T, NF>) {
     ox_n = td.off[r];
     oy_n = td.off[n + r];
     s0_n = td.sig[r];
@@ -277,7 +284,7 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
     T ox, oy, ga[M], sp, sm, ratio;
-    if (kPrefetch<NF>) {
+    if (kPrefetchGP<T, NF>) {
       ox = ox_n;
       oy = oy_n;
       sp = s0_n;
@@ -529,12 +536,13 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double
 // KIND: 0 WENO on the conserved variables, 1 the linear scheme, 2 WENO on
 // the characteristic variables (Euler).
 template <typename T, int NF, int V, int KIND>
-// Occupancy measured on gfx950 (FP32): the conserved-variable quadrilateral
-// kernel runs fastest with the whole register file (its candidate state
-// fits the 256 VGPRs of 2 waves per SIMD by itself), the triangle kernels
-// and the characteristic quadrilateral kernel with 2 waves per SIMD forced
-// (the latter then spills one 4-byte value and runs 39% faster than at 1).
-__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && (NF == 3 || KIND == 2) ? 2 : 1) void k_recon(
+// Occupancy measured on gfx950 (FP32): the WENO kernels run fastest with 2
+// waves per SIMD forced (256 VGPRs each; the quadrilateral ones then spill a
+// few values: the characteristic kernel runs 39% faster than at 1 wave, the
+// conserved one, which reads its weights one point ahead, 4% faster than
+// without that prefetch, when it fitted 2 waves unspilled).  The FP32 linear
+// kernels and every FP64 kernel keep the whole register file.
+__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && (NF == 3 || KIND != 1) ? 2 : 1) void k_recon(
     const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
   extern __shared__ double lds[];
   const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
