@@ -63,6 +63,15 @@ __device__ inline double rcp(double x) {
   return r;
 }
 
+// a / b and sqrt(x) in the flux: FP32 takes the hardware reciprocal and
+// square root (1 ulp; the correctly rounded sequences made the flux kernel 8%
+// slower once its face states came from LDS), FP64 the correctly rounded
+// operations.
+__device__ inline float fdiv(float a, float b) { return a * __builtin_amdgcn_rcpf(b); }
+__device__ inline double fdiv(double a, double b) { return a / b; }
+__device__ inline float fsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double fsqrt(double x) { return sqrt(x); }
+
 template <typename T, int V>
 __device__ inline void store_state(T* p, const T* x) {
 #pragma unroll
@@ -591,16 +600,16 @@ __global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && (NF == 3 || KIND != 1
 template <typename T>
 __device__ inline void hllc(const T* WL, const T* WR, T nx, T ny, T gam, T* f) {
   const T rL = WL[0], rR = WR[0];
-  const T irL = T(1) / rL, irR = T(1) / rR;
+  const T irL = fdiv(T(1), rL), irR = fdiv(T(1), rR);
   const T uL = (WL[1] * nx + WL[2] * ny) * irL, vL = (-WL[1] * ny + WL[2] * nx) * irL;
   const T uR = (WR[1] * nx + WR[2] * ny) * irR, vR = (-WR[1] * ny + WR[2] * nx) * irR;
   const T EL = WL[3], ER = WR[3];
   const T pL = (gam - T(1)) * (EL - T(0.5) * rL * (uL * uL + vL * vL));
   const T pR = (gam - T(1)) * (ER - T(0.5) * rR * (uR * uR + vR * vR));
-  const T aL = sqrt(gam * pL * irL), aR = sqrt(gam * pR * irR);
+  const T aL = fsqrt(gam * pL * irL), aR = fsqrt(gam * pR * irR);
   const T SL = fmin(uL - aL, uR - aR), SR = fmax(uL + aL, uR + aR);
-  const T Ss = (pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR)) /
-               (rL * (SL - uL) - rR * (SR - uR));
+  const T Ss = fdiv(pR - pL + rL * uL * (SL - uL) - rR * uR * (SR - uR),
+                    rL * (SL - uL) - rR * (SR - uR));
   if (T(0) <= SL) {
     f[0] = rL * uL;
     f[1] = rL * uL * uL + pL;
@@ -610,20 +619,20 @@ __device__ inline void hllc(const T* WL, const T* WR, T nx, T ny, T gam, T* f) {
     // F*_L = F_L + S_L (U*_L - U_L), with U*_L - U_L written in terms of
     // d = S* - u_L so that it vanishes exactly for equal states
     const T d = Ss - uL;
-    const T cm = rL * d / (SL - Ss);   // rho*_L - rho_L
+    const T cm = fdiv(rL * d, SL - Ss);   // rho*_L - rho_L
     f[0] = rL * uL + SL * cm;
     f[1] = rL * uL * uL + pL + SL * (cm * Ss + rL * d);
     f[2] = rL * uL * vL + SL * (cm * vL);
     f[3] = (EL + pL) * uL +
-           SL * (EL * irL * cm + (rL + cm) * d * (Ss + pL / (rL * (SL - uL))));
+           SL * (EL * irL * cm + (rL + cm) * d * (Ss + fdiv(pL, rL * (SL - uL))));
   } else if (T(0) < SR) {
     const T d = Ss - uR;
-    const T cm = rR * d / (SR - Ss);   // rho*_R - rho_R
+    const T cm = fdiv(rR * d, SR - Ss);   // rho*_R - rho_R
     f[0] = rR * uR + SR * cm;
     f[1] = rR * uR * uR + pR + SR * (cm * Ss + rR * d);
     f[2] = rR * uR * vR + SR * (cm * vR);
     f[3] = (ER + pR) * uR +
-           SR * (ER * irR * cm + (rR + cm) * d * (Ss + pR / (rR * (SR - uR))));
+           SR * (ER * irR * cm + (rR + cm) * d * (Ss + fdiv(pR, rR * (SR - uR))));
   } else {
     f[0] = rR * uR;
     f[1] = rR * uR * uR + pR;
@@ -657,82 +666,110 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
 // kernel runs 8% slower on meshes without such faces when the front case is
 // compiled in, although it never executes, so it has an instantiation
 // without it.
+//
+// Each tile first copies its cells' face-state records (contiguous in FS) to
+// LDS in 16-byte units: a thread's own record and every neighbour inside the
+// tile are then read from LDS, and only neighbours in other tiles from FS.
+// Measured on gfx950: reading each face's states from FS instead took 18%
+// longer (the lines of a wave's 64 records, 32 bytes used per face, were
+// fetched again for later faces).
 template <typename T, int V, int MODE, bool FRONTS>
 __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
                                                      const T* __restrict__ FS, const double* W_in,
                                                      const double* Wn, double* W_out,
                                                      const double* __restrict__ dtp, int* flag) {
+  extern __shared__ double lds[];
+  T* rec = reinterpret_cast<T*>(lds);
+  constexpr int REC = 8 * V;              // face-state values per cell
+  constexpr int PER = 16 / sizeof(T);     // values per 16-byte unit
+  constexpr int STRIDE = REC + PER;       // LDS row per cell, padded against bank conflicts
   const int64_t N = m.N;
   const int ntiles = m.n_tq + m.n_tt;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const Tile tl = m.tiles[tile];
-    if ((int)threadIdx.x >= tl.count) continue;
-    const int64_t i = tl.first + threadIdx.x;
     const int nf = tile < m.n_tq ? 4 : 3;
-    double acc[V];
-#pragma unroll
-    for (int v = 0; v < V; ++v) acc[v] = 0.0;
-    bool bad = false;
-    for (int k = 0; k < nf; ++k) {
-      const int32_t pk = m.fnb[k * N + i];
-      const T nx = m.fnrm[(k * 2 + 0) * N + i];
-      const T ny = m.fnrm[(k * 2 + 1) * N + i];
-      const double coef = m.fcoef[k * N + i];
-      T o0[V], o1[V], t0[V], t1[V];
-      load_state<T, V>(FS + (i * 8 + 2 * k) * V, o0);
-      load_state<T, V>(FS + (i * 8 + 2 * k + 1) * V, o1);
-      bool left = true;
-      if (pk < 0) {
-        // boundary face: the outside states (the stored normal is the cell's)
-        outside_state<T, V, T, FRONTS>(pk, o0, nx, ny, m, t0);
-        outside_state<T, V, T, FRONTS>(pk, o1, nx, ny, m, t1);
-      } else {
-        const int64_t c = pk >> 3;
-        const int kp = (pk >> 1) & 3;
-        left = (pk & 1) != 0;
-        // the neighbour's Gauss points run the other way along the face
-        load_state<T, V>(FS + (c * 8 + 2 * kp + 1) * V, t0);
-        load_state<T, V>(FS + (c * 8 + 2 * kp) * V, t1);
+    {
+      // the units of each record that hold the 2 nf Gauss-point slots
+      const int U = (2 * nf * V + PER - 1) / PER;
+      const int n16 = tl.count * U;
+      const int4* src = reinterpret_cast<const int4*>(FS + (int64_t)tl.first * REC);
+      for (int q = threadIdx.x; q < n16; q += blockDim.x) {
+        const int c = q / U, u = q - c * U;
+        *reinterpret_cast<int4*>(rec + c * STRIDE + u * PER) = src[c * (REC / PER) + u];
       }
-      if constexpr (V == 4) {
-        // an inadmissible reconstruction (the scheme is not positivity
-        // preserving): density or pressure not positive at a Gauss point
-        const T g1 = (T)p.gamma - T(1);
-        const T p0 = g1 * (o0[3] - T(0.5) * (o0[1] * o0[1] + o0[2] * o0[2]) / o0[0]);
-        const T p1 = g1 * (o1[3] - T(0.5) * (o1[1] * o1[1] + o1[2] * o1[2]) / o1[0]);
-        bad |= !(o0[0] > T(0)) || !(o1[0] > T(0)) || !(p0 > T(0)) || !(p1 > T(0));
-      }
-      double F0[V], F1[V];
-      if (left) {
-        face_flux<T, V>(o0, t0, nx, ny, p, F0);
-        face_flux<T, V>(o1, t1, nx, ny, p, F1);
-      } else {
-        face_flux<T, V>(t0, o0, nx, ny, p, F0);
-        face_flux<T, V>(t1, o1, nx, ny, p, F1);
-      }
-      const double sc = left ? coef : -coef;
-#pragma unroll
-      for (int v = 0; v < V; ++v) acc[v] += sc * (F0[v] + F1[v]);
     }
-    double dt = 0.0;
-    if (MODE != 0) dt = dtp[tl.inst];
+    __syncthreads();
+    if ((int)threadIdx.x < tl.count) {
+      const int64_t i = tl.first + threadIdx.x;
+      const T* own = rec + threadIdx.x * STRIDE;
+      double acc[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const double Lv = -acc[v];
-      double out;
-      if (MODE == 0) {
-        out = Lv;
-      } else if (MODE == 1) {
-        out = W_in[v * N + i] + dt * Lv;
-      } else if (MODE == 2) {
-        out = 0.75 * Wn[v * N + i] + 0.25 * (W_in[v * N + i] + dt * Lv);
-      } else {
-        out = Wn[v * N + i] / 3.0 + 2.0 / 3.0 * (W_in[v * N + i] + dt * Lv);
+      for (int v = 0; v < V; ++v) acc[v] = 0.0;
+      bool bad = false;
+      for (int k = 0; k < nf; ++k) {
+        const int32_t pk = m.fnb[k * N + i];
+        const T nx = m.fnrm[(k * 2 + 0) * N + i];
+        const T ny = m.fnrm[(k * 2 + 1) * N + i];
+        const double coef = m.fcoef[k * N + i];
+        T o0[V], o1[V], t0[V], t1[V];
+        load_state<T, V>(own + 2 * k * V, o0);
+        load_state<T, V>(own + (2 * k + 1) * V, o1);
+        bool left = true;
+        if (pk < 0) {
+          // boundary face: the outside states (the stored normal is the cell's)
+          outside_state<T, V, T, FRONTS>(pk, o0, nx, ny, m, t0);
+          outside_state<T, V, T, FRONTS>(pk, o1, nx, ny, m, t1);
+        } else {
+          const int64_t c = pk >> 3;
+          const int kp = (pk >> 1) & 3;
+          left = (pk & 1) != 0;
+          // the neighbour's Gauss points run the other way along the face
+          const int64_t lc = c - tl.first;
+          const T* nb = (uint64_t)lc < (uint64_t)tl.count ? rec + lc * STRIDE : FS + c * REC;
+          load_state<T, V>(nb + (2 * kp + 1) * V, t0);
+          load_state<T, V>(nb + 2 * kp * V, t1);
+        }
+        if constexpr (V == 4) {
+          // an inadmissible reconstruction (the scheme is not positivity
+          // preserving): density or pressure not positive at a Gauss point
+          // (p > 0 with rho > 0 is 2 rho E > |m|^2, as gamma > 1)
+          const T e0 = T(2) * o0[0] * o0[3] - (o0[1] * o0[1] + o0[2] * o0[2]);
+          const T e1 = T(2) * o1[0] * o1[3] - (o1[1] * o1[1] + o1[2] * o1[2]);
+          bad |= !(o0[0] > T(0)) || !(o1[0] > T(0)) || !(e0 > T(0)) || !(e1 > T(0));
+        }
+        double F0[V], F1[V];
+        if (left) {
+          face_flux<T, V>(o0, t0, nx, ny, p, F0);
+          face_flux<T, V>(o1, t1, nx, ny, p, F1);
+        } else {
+          face_flux<T, V>(t0, o0, nx, ny, p, F0);
+          face_flux<T, V>(t1, o1, nx, ny, p, F1);
+        }
+        const double sc = left ? coef : -coef;
+#pragma unroll
+        for (int v = 0; v < V; ++v) acc[v] += sc * (F0[v] + F1[v]);
       }
-      bad |= !isfinite(out);
-      W_out[v * N + i] = out;
+      double dt = 0.0;
+      if (MODE != 0) dt = dtp[tl.inst];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const double Lv = -acc[v];
+        double out;
+        if (MODE == 0) {
+          out = Lv;
+        } else if (MODE == 1) {
+          out = W_in[v * N + i] + dt * Lv;
+        } else if (MODE == 2) {
+          out = 0.75 * Wn[v * N + i] + 0.25 * (W_in[v * N + i] + dt * Lv);
+        } else {
+          out = Wn[v * N + i] * (1.0 / 3.0) + 2.0 / 3.0 * (W_in[v * N + i] + dt * Lv);
+        }
+        bad |= !isfinite(out);
+        W_out[v * N + i] = out;
+      }
+      if (bad && flag) *flag = 1;
     }
-    if (bad && flag) *flag = 1;
+    __syncthreads();   // the next tile overwrites the records
   }
 }
 
@@ -886,13 +923,16 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
   const int ntiles = m.n_tq + m.n_tt;
   if (ntiles <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
+  // one padded record row per cell of a tile
+  const size_t shm = (size_t)kTileCells * (8 * nvar * sizeof(T) + 16);
+  if (shm > lds_limit()) return hipErrorInvalidConfiguration;
   // meshes without front faces get the instantiation without the front case
   auto go = [&](auto v_tag, auto mode_tag) {
     constexpr int V = decltype(v_tag)::value, MD = decltype(mode_tag)::value;
     if (m.fronts)
-      k_flux<T, V, MD, true><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+      k_flux<T, V, MD, true><<<grid, kTileCells, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
     else
-      k_flux<T, V, MD, false><<<grid, kTileCells, 0, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+      k_flux<T, V, MD, false><<<grid, kTileCells, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
   };
   auto by_mode = [&](auto v_tag) {
     switch (mode) {
