@@ -202,13 +202,6 @@ __device__ inline void ghost_differences(const MeshDev<T>& m, int64_t i, const d
 template <int NF>
 constexpr bool kPrefetch = NF == 3;
 
-// Each Gauss point's offsets and weights are fetched one point ahead by the
-// triangle kernels and by the FP32 quadrilateral kernel (there at the cost
-// of a 24-byte spill per lane, 4% faster than reading them when needed); the
-// FP64 quadrilateral kernel reads them when needed (ahead they spill).
-template <typename T, int NF>
-constexpr bool kPrefetchGP = NF == 3 || sizeof(T) == 4;
-
 template <typename T, int NF>
 struct WenoIn {
   int li[Layout<NF>::S];       // LDS positions of the stencil cells
@@ -249,17 +242,15 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
   using L = Layout<NF>;
   constexpr int S = L::S, M = L::M, G = 2 * NF;
   const int64_t n = td.Nt;
-  // the first Gauss point's weights and offsets (prefetching kernel)
-  T ga_n[M], ox_n = 0, oy_n = 0, s0_n = 0, s1_n = 0, s2_n = 0;
-  if (kPrefetchGP<T, NF>) {
-    ox_n = td.off[r];
-    oy_n = td.off[n + r];
-    s0_n = td.sig[r];
-    s1_n = td.sig[n + r];
-    s2_n = td.sig[2 * n + r];
+  // Each Gauss point's offsets and weights are fetched one point ahead.
+  // Measured on gfx950: the quadrilateral kernels then spill a few values
+  // (24 bytes per lane in FP32, 12 in FP64) and still run 4% (FP32) and 30%
+  // (FP64) faster than with the loads at the point itself, where the FP64
+  // kernel, at one wave per SIMD, waited for each weight's load in turn.
+  T ga_n[M], ox_n = td.off[r], oy_n = td.off[n + r];
+  T s0_n = td.sig[r], s1_n = td.sig[n + r], s2_n = td.sig[2 * n + r];
 #pragma unroll
-    for (int j = 0; j < M; ++j) ga_n[j] = td.gam[j * n + r];
-  }
+  for (int j = 0; j < M; ++j) ga_n[j] = td.gam[j * n + r];
   // per-cell inputs: prefetched, or read here
   auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)td.lidx[s * n + r]; };
   auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : td.Y[(j * 4 + k) * n + r]; };
@@ -292,32 +283,18 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
   }
 #pragma unroll 1
   for (int g = 0; g < G; ++g) {
-    T ox, oy, ga[M], sp, sm, ratio;
-    if (kPrefetchGP<T, NF>) {
-      ox = ox_n;
-      oy = oy_n;
-      sp = s0_n;
-      sm = s1_n;
-      ratio = s2_n;
+    const T ox = ox_n, oy = oy_n, sp = s0_n, sm = s1_n, ratio = s2_n;
+    T ga[M];
 #pragma unroll
-      for (int j = 0; j < M; ++j) ga[j] = ga_n[j];
-      if (g + 1 < G) {
-        ox_n = td.off[(2 * g + 2) * n + r];
-        oy_n = td.off[(2 * g + 3) * n + r];
-        s0_n = td.sig[(3 * g + 3) * n + r];
-        s1_n = td.sig[(3 * g + 4) * n + r];
-        s2_n = td.sig[(3 * g + 5) * n + r];
+    for (int j = 0; j < M; ++j) ga[j] = ga_n[j];
+    if (g + 1 < G) {
+      ox_n = td.off[(2 * g + 2) * n + r];
+      oy_n = td.off[(2 * g + 3) * n + r];
+      s0_n = td.sig[(3 * g + 3) * n + r];
+      s1_n = td.sig[(3 * g + 4) * n + r];
+      s2_n = td.sig[(3 * g + 5) * n + r];
 #pragma unroll
-        for (int j = 0; j < M; ++j) ga_n[j] = td.gam[((g + 1) * M + j) * n + r];
-      }
-    } else {
-      ox = td.off[(2 * g) * n + r];
-      oy = td.off[(2 * g + 1) * n + r];
-      sp = td.sig[(3 * g) * n + r];
-      sm = td.sig[(3 * g + 1) * n + r];
-      ratio = td.sig[(3 * g + 2) * n + r];
-#pragma unroll
-      for (int j = 0; j < M; ++j) ga[j] = td.gam[(g * M + j) * n + r];
+      for (int j = 0; j < M; ++j) ga_n[j] = td.gam[((g + 1) * M + j) * n + r];
     }
     T gp[M], gm[M];
     split_weights<T, M>(ga, theta, ratio, gp, gm);
@@ -667,12 +644,14 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
 // compiled in, although it never executes, so it has an instantiation
 // without it.
 //
-// Each tile first copies its cells' face-state records (contiguous in FS) to
-// LDS in 16-byte units: a thread's own record and every neighbour inside the
-// tile are then read from LDS, and only neighbours in other tiles from FS.
-// Measured on gfx950: reading each face's states from FS instead took 18%
-// longer (the lines of a wave's 64 records, 32 bytes used per face, were
-// fetched again for later faces).
+// In FP32 each tile first copies its cells' face-state records (contiguous in
+// FS) to LDS in 16-byte units: a thread's own record and every neighbour
+// inside the tile are then read from LDS, and only neighbours in other tiles
+// from FS.  Measured on gfx950: reading each face's states from FS instead
+// took 18% longer (the lines of a wave's 64 records, 32 bytes used per face,
+// were fetched again for later faces).  The FP64 kernel reads FS directly:
+// its 256-byte records would fill 68 KB of LDS per block, and at two blocks
+// per CU it ran 25% slower.
 template <typename T, int V, int MODE, bool FRONTS>
 __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
                                                      const T* __restrict__ FS, const double* W_in,
@@ -683,12 +662,13 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
   constexpr int REC = 8 * V;              // face-state values per cell
   constexpr int PER = 16 / sizeof(T);     // values per 16-byte unit
   constexpr int STRIDE = REC + PER;       // LDS row per cell, padded against bank conflicts
+  constexpr bool STAGE = sizeof(T) == 4;  // records staged in LDS
   const int64_t N = m.N;
   const int ntiles = m.n_tq + m.n_tt;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const Tile tl = m.tiles[tile];
     const int nf = tile < m.n_tq ? 4 : 3;
-    {
+    if (STAGE) {
       // the units of each record that hold the 2 nf Gauss-point slots
       const int U = (2 * nf * V + PER - 1) / PER;
       const int n16 = tl.count * U;
@@ -701,7 +681,7 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
     __syncthreads();
     if ((int)threadIdx.x < tl.count) {
       const int64_t i = tl.first + threadIdx.x;
-      const T* own = rec + threadIdx.x * STRIDE;
+      const T* own = STAGE ? rec + threadIdx.x * STRIDE : FS + i * REC;
       double acc[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] = 0.0;
@@ -725,7 +705,8 @@ __global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
           left = (pk & 1) != 0;
           // the neighbour's Gauss points run the other way along the face
           const int64_t lc = c - tl.first;
-          const T* nb = (uint64_t)lc < (uint64_t)tl.count ? rec + lc * STRIDE : FS + c * REC;
+          const T* nb =
+              STAGE && (uint64_t)lc < (uint64_t)tl.count ? rec + lc * STRIDE : FS + c * REC;
           load_state<T, V>(nb + (2 * kp + 1) * V, t0);
           load_state<T, V>(nb + 2 * kp * V, t1);
         }
@@ -923,8 +904,8 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
   const int ntiles = m.n_tq + m.n_tt;
   if (ntiles <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
-  // one padded record row per cell of a tile
-  const size_t shm = (size_t)kTileCells * (8 * nvar * sizeof(T) + 16);
+  // one padded record row per cell of a tile (FP32)
+  const size_t shm = sizeof(T) == 4 ? (size_t)kTileCells * (8 * nvar * sizeof(T) + 16) : 0;
   if (shm > lds_limit()) return hipErrorInvalidConfiguration;
   // meshes without front faces get the instantiation without the front case
   auto go = [&](auto v_tag, auto mode_tag) {
