@@ -44,8 +44,7 @@ def log(msg):
 # indices 4(S-1), Gauss-point offsets 4n, candidate operators 4M and linear
 # weights 2nM values of p bytes, and the cell's own state V * 8 bytes.  The
 # split sums the kernel also reads (3 per Gauss point) and the face states it
-# writes for the flux kernel are implementation traffic and are not counted.  Face states written for the flux kernel
-# are implementation traffic and are not counted.
+# writes for the flux kernel are implementation traffic and are not counted.
 def recon_bytes(nf, p, nvar):
     S, M = (13, 12) if nf == 4 else (10, 9)
     return 4 * (S - 1) + p * (4 * nf + 4 * M + 2 * nf * M) + nvar * 8
