@@ -126,7 +126,11 @@ typedef struct {
 
 /* Physics: equation = UW_ADVECTION (u_t + ax u_x + ay u_y = 0, upwind flux)
  * or UW_EULER (2D Euler, eq. (hyperbolic), HLLC flux, ratio `gamma`);
- * precision = UW_FP64 or UW_FP32. */
+ * precision = UW_FP64 or UW_FP32.  UW_FP32 reconstructs and evaluates the
+ * flux in FP32 (reciprocals, divisions and square roots with the hardware's
+ * 1-ulp instructions) and keeps the state, the residual gather and the RK
+ * stages in FP64; UW_FP64 does everything in FP64 with correctly rounded
+ * divisions and square roots. */
 typedef struct {
   int32_t equation;
   double ax, ay, gamma;
