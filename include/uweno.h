@@ -129,8 +129,9 @@ typedef struct {
  * precision = UW_FP64 or UW_FP32.  UW_FP32 reconstructs and evaluates the
  * flux in FP32 (reciprocals, divisions and square roots with the hardware's
  * 1-ulp instructions) and keeps the state, the residual gather and the RK
- * stages in FP64; UW_FP64 does everything in FP64 with correctly rounded
- * divisions and square roots. */
+ * stages in FP64; UW_FP64 does everything in FP64 (the reconstruction's
+ * reciprocals as the hardware's refined by two Newton steps, the flux's
+ * divisions and square roots correctly rounded). */
 typedef struct {
   int32_t equation;
   double ax, ay, gamma;
