@@ -135,6 +135,31 @@ def _ptr(t):
     return t.data_ptr()
 
 
+def _device_buffer(x, device, numel, name, at_least=False):
+    """Checks a device argument before its address reaches the library,
+    which cannot check device pointers: a contiguous FP64 torch tensor on
+    the mesh's device holding exactly `numel` values (at least, for
+    at_least).  Raises ValueError otherwise."""
+    import torch
+    if not isinstance(x, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor on cuda:{device}, got {type(x).__name__}")
+    if x.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64, got {x.dtype}")
+    if not x.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if (x.numel() < numel) if at_least else (x.numel() != numel):
+        want = f"at least {numel}" if at_least else str(numel)
+        raise ValueError(f"{name} must hold {want} values, has {x.numel()}")
+    if not x.is_cuda or x.device.index != device:
+        raise ValueError(f"{name} must be on cuda:{device}, is on {x.device}")
+
+
+def _nvar(physics):
+    """Variables per cell of an equation, or None for an unknown one (the
+    library rejects it)."""
+    return {UW_EULER: 4, UW_ADVECTION: 1}.get(int(physics.equation))
+
+
 def _stream(stream):
     if stream is None:
         import torch
@@ -230,8 +255,21 @@ class Mesh:
     def to_original(self, W):
         return np.asarray(W)[:, self.new_of_old]
 
+    def _check_state(self, physics, **bufs):
+        # host-only meshes (device < 0) are left to the library, which
+        # rejects device calls on them
+        nv = _nvar(physics)
+        if self.device < 0 or nv is None:
+            return
+        for name, x in bufs.items():
+            if name in ("t_dev", "dt_dev"):
+                _device_buffer(x, self.device, 1, name, at_least=True)
+            else:
+                _device_buffer(x, self.device, nv * self.n_cells, name)
+
     def residual(self, physics: PhysicsC, W, L, stream=None, t=None):
         """L = L(W); at time t (moving-front boundaries) when t is given."""
+        self._check_state(physics, W=W, L=L)
         if t is None:
             _check(LIB.uw_residual(self.handle, ctypes.byref(physics), _ptr(W), _ptr(L),
                                    _stream(stream)))
@@ -241,10 +279,12 @@ class Mesh:
 
     def rk3_step(self, physics: PhysicsC, W, t_dev, cfl=0.5, dt_fixed=0.0, t_end=float("inf"),
                  stream=None):
+        self._check_state(physics, W=W, t_dev=t_dev)
         _check(LIB.uw_rk3_step(self.handle, ctypes.byref(physics), _ptr(W), cfl, dt_fixed, t_end,
                                _ptr(t_dev), _stream(stream)))
 
     def cfl_dt(self, physics: PhysicsC, W, cfl, dt_dev, stream=None):
+        self._check_state(physics, W=W, dt_dev=dt_dev)
         _check(LIB.uw_cfl_dt(self.handle, ctypes.byref(physics), _ptr(W), cfl, _ptr(dt_dev),
                              _stream(stream)))
 
@@ -279,6 +319,7 @@ class Batch:
 
     def __init__(self, meshes, physics: PhysicsC):
         self.meshes = list(meshes)
+        self.nvar = _nvar(physics)
         arr = (ctypes.c_void_p * len(self.meshes))(*[m.handle.value for m in self.meshes])
         h = ctypes.c_void_p()
         _check(LIB.uw_batch_create(arr, len(self.meshes), ctypes.byref(physics), ctypes.byref(h)))
@@ -305,6 +346,10 @@ class Batch:
 
     def rk3_step(self, W, t_dev, cfl=0.5, dt_fixed=0.0, t_end=float("inf"), n_steps=1,
                  stream=None):
+        dev = self.meshes[0].device
+        if dev >= 0 and self.nvar is not None:
+            _device_buffer(W, dev, self.nvar * int(self.offsets[-1]), "W")
+            _device_buffer(t_dev, dev, len(self.meshes), "t_dev", at_least=True)
         _check(LIB.uw_batch_rk3_step(self.handle, _ptr(W), cfl, dt_fixed, t_end, n_steps,
                                      _ptr(t_dev), _stream(stream)))
 
