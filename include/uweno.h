@@ -23,6 +23,11 @@
  *   uw_check, which synchronises the stream.
  * - Ownership: host inputs are borrowed for the duration of the call and
  *   copied; device tables belong to the mesh until uw_mesh_destroy.
+ * - Concurrency: different meshes and batches may be used from different
+ *   threads at once; calls on one mesh, or on one batch, must not overlap:
+ *   they share its work buffers, captured graphs and error flag.  Device
+ *   work on one mesh or batch queued on different streams must be ordered
+ *   by the caller for the same reason.
  */
 #ifndef UWENO_H
 #define UWENO_H
