@@ -195,6 +195,35 @@ def eigenvectors(u, v, H, c, nx, ny, gamma):
 # reconstruction (WENO or linear) at the Gauss points of a group of cells
 # --------------------------------------------------------------------------
 
+def split_linear_weights(gam, theta):
+    """Split of the optimised linear weights (Sec. 3.4) along the last axis:
+    gamma~+ = (gamma + theta |gamma|)/2, gamma~- = gamma~+ - gamma, their
+    sums sigma^pm, and the scaled non-negative weights gamma^pm =
+    gamma~pm / sigma^pm.  Returns (gamma^+, sigma^+, gamma^-, sigma^-), the
+    sums with a kept last axis of length one."""
+    gam = np.asarray(gam, dtype=np.float64)
+    tp = 0.5 * (gam + theta * np.abs(gam))
+    tm = tp - gam
+    sp = tp.sum(axis=-1, keepdims=True)
+    sm = tm.sum(axis=-1, keepdims=True)
+    return tp / sp, sp, tm / sm, sm
+
+
+def new_smoothness_indicator(beta, gw):
+    """The smoothness indicator of Sec. 3.4 that takes the linear weight into
+    account: beta~ = beta (1 + gamma beta + (gamma beta)^2), gamma one of the
+    scaled split weights gamma^pm of the candidate."""
+    t = gw * beta
+    return beta * (1.0 + t + t * t)
+
+
+def nonlinear_weights(gw, beta, eps):
+    """delta_j = alpha_j / sum_l alpha_l with alpha_j = gamma_j / (beta~_j +
+    eps)^2 (Sec. 3.4), over the last axis (the candidates)."""
+    alpha = gw / (new_smoothness_indicator(beta, gw) + eps) ** 2
+    return alpha / alpha.sum(axis=-1, keepdims=True)
+
+
 def _nonlinear_combination(gp, sp, gm, sm, beta, d, eps):
     """sum over signs of sign sigma^pm sum_j delta_j^pm d_j, with the new
     smoothness indicator of Sec. 3.4.  gp, gm: [m,G,M] normalised split
@@ -202,12 +231,29 @@ def _nonlinear_combination(gp, sp, gm, sm, beta, d, eps):
     d: [F,m,G,M] candidate increments P_j(x_G) - W_i0 (F fields)."""
     out = 0.0
     for gw, sig, sgn in ((gp, sp, 1.0), (gm, sm, -1.0)):
-        t = gw[None] * beta
-        bt = beta * (1.0 + t + t * t)
-        alpha = gw[None] / (bt + eps) ** 2
-        delta = alpha / alpha.sum(axis=-1, keepdims=True)
+        delta = nonlinear_weights(gw[None], beta, eps)
         out = out + sgn * sig[None, :, :, 0] * (delta * d).sum(axis=-1)
     return out                                          # [F,m,G]
+
+
+def candidate_gradients(g, dW, rows):
+    """Gradients and smoothness indicators of the linear candidates (Sec. 3.1,
+    3.2, 3.4) of the given rows of a cell group, from the stencil differences
+    dW [V,m,S] (dW[..., s] = W of stencil slot s minus W_i0).  Candidate j
+    over {i0, a, b} has, in the scaled frame of the target cell, the
+    gradient g_j = Y_j (dW_a, dW_b).  With K = 1 the indicator of Sec. 3.4 is
+    beta_j = int_Omega |grad P_j|^2 = |Omega| |grad P_j|^2 (the gradient of a
+    linear P is constant), and in coordinates scaled by sqrt|Omega| the
+    gradient is g_j = sqrt|Omega| grad P_j, so beta_j = |g_j|^2.
+    Returns gx, gy, beta, each [V,m,M]."""
+    Y = g.Y[rows]                                       # [m,M,2,2]
+    V, m = dW.shape[0], dW.shape[1]
+    M = g.st.spec.M
+    dWa = dW[:, :, g.cand_a]                            # [V,m,M]
+    dWb = np.take_along_axis(dW, np.broadcast_to(g.cand_b[rows][None], (V, m, M)), axis=2)
+    gx = Y[None, :, :, 0, 0] * dWa + Y[None, :, :, 0, 1] * dWb
+    gy = Y[None, :, :, 1, 0] * dWa + Y[None, :, :, 1, 1] * dWb
+    return gx, gy, gx * gx + gy * gy
 
 
 def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None, t=0.0):
@@ -225,26 +271,13 @@ def _weno_group(g, W, scheme, rows, gamma=1.4, mesh=None, t=0.0):
         nrm = g.normal[rows][:, k]
         ghost = outside_state(mesh, cells, k, W0, nrm[:, 0], nrm[:, 1], t)
         dW[:, :, k + 1] = np.where(b[None], ghost - W0, dW[:, :, k + 1])
-    Y = g.Y[rows]                                       # [m,M,2,2]
     off = g.gp_off[rows]                                # [m,G,2]
-    M = st.spec.M
-    m = cells.size
     if scheme.mode == "linear":
         eta = g.eta[rows]                               # [m,G,S]
         return W0[:, :, None] + np.einsum("mgs,vms->vmg", eta[:, :, 1:], dW[:, :, 1:])
-    dWa = dW[:, :, g.cand_a]                            # [V,m,M]
-    dWb = np.take_along_axis(dW, np.broadcast_to(g.cand_b[rows][None], (W.shape[0], m, M)), axis=2)
-    gx = Y[None, :, :, 0, 0] * dWa + Y[None, :, :, 0, 1] * dWb
-    gy = Y[None, :, :, 1, 0] * dWa + Y[None, :, :, 1, 1] * dWb
-    beta = gx * gx + gy * gy                             # [V,m,M]
-    gam = g.gamma[rows]                                 # [m,G,M]
-    tp = 0.5 * (gam + scheme.theta * np.abs(gam))
-    tm = tp - gam
-    sp = tp.sum(axis=-1, keepdims=True)
-    sm = tm.sum(axis=-1, keepdims=True)
-    gp = tp / sp
-    gm = tm / sm
-    G = gam.shape[1]
+    gx, gy, beta = candidate_gradients(g, dW, rows)      # [V,m,M]
+    gp, sp, gm, sm = split_linear_weights(g.gamma[rows], scheme.theta)   # [m,G,M], [m,G,1]
+    G = gp.shape[1]
     # P_j(x_G) - W_i0 at every point: [V,m,G,M]
     d = off[None, :, :, None, 0] * gx[:, :, None, :] + off[None, :, :, None, 1] * gy[:, :, None, :]
     if scheme.variables == "characteristic" and W.shape[0] == 4:

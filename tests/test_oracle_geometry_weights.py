@@ -226,22 +226,6 @@ def test_optimisation_tames_large_weights():
         assert d["resid_opt"] < 1e-9 and d["sum_dev"] < 1e-10
 
 
-def test_split_weights_closed_form():
-    """Sec. 3.4 with theta = 3: gamma >= 0 gives (2 gamma, gamma), gamma < 0
-    gives (|gamma|, 2|gamma|); gamma^pm >= 0 sum to one and
-    sigma^+ - sigma^- = sum gamma."""
-    rng = np.random.Generator(np.random.PCG64(4))
-    gam = rng.normal(size=(100, 12))
-    gam /= gam.sum(axis=1, keepdims=True)
-    tp = 0.5 * (gam + 3 * np.abs(gam))
-    tm = tp - gam
-    np.testing.assert_allclose(tp, np.where(gam >= 0, 2 * gam, -gam), atol=1e-15)
-    np.testing.assert_allclose(tm, np.where(gam >= 0, gam, -2 * gam), atol=1e-15)
-    sp, sm = tp.sum(1), tm.sum(1)
-    assert (tp / sp[:, None] >= 0).all() and (tm / sm[:, None] >= 0).all()
-    np.testing.assert_allclose(sp - sm, gam.sum(1), atol=1e-13)
-
-
 def test_tikhonov_limit_is_pseudo_inverse():
     """Remark after eq. (quadratic-2): the regularised solution differs from
     the unregularised one by O(zeta); in the limit it is the pseudo-inverse."""

@@ -66,34 +66,6 @@ def test_linear_data_is_reconstructed_exactly(mixed_tables):
                 assert abs(R[c][0, 2 * k + q] - lin(*x)) < 1e-9
 
 
-def test_jump_crossing_candidates_lose_weight():
-    """Sec. 3.4 (ratio argument): a candidate whose sub-stencil crosses a jump
-    gets a nonlinear weight far below its linear weight."""
-    mesh = wl.grid_mesh(12, 12, 2.0, 2.0, "quad", 0.1, 43, True)
-    T = ow.precompute(mesh)
-    W = wl.cell_averages(mesh, lambda x, y: np.where(x < 1.0, 1.0, 2.0)[None], 1, q=3)
-    g = T.groups[4]
-    # a cell just left of the jump x = 1
-    cx = g.frame.centroid[:, 0]
-    r = int(np.argmin(np.abs(cx - (1.0 - 2.0 / 24)) + np.abs(g.frame.centroid[:, 1] - 1.0)))
-    rc = g.st.runtime_cell[r]
-    dW = W[0, rc] - W[0, g.st.cells[r]]
-    dWa = dW[g.cand_a]
-    dWb = dW[g.cand_b[r]]
-    gx = g.Y[r, :, 0, 0] * dWa + g.Y[r, :, 0, 1] * dWb
-    gy = g.Y[r, :, 1, 0] * dWa + g.Y[r, :, 1, 1] * dWb
-    beta = gx * gx + gy * gy
-    crossing = beta > 0.1            # the sub-stencil spans the unit jump
-    assert crossing.any() and (~crossing).any()
-    gam = g.gamma[r, 0]
-    tp = 0.5 * (gam + 3 * np.abs(gam))
-    gp = tp / tp.sum()
-    bt = beta * (1 + gp * beta + (gp * beta) ** 2)
-    alpha = gp / (bt + T.scheme.eps) ** 2
-    delta = alpha / alpha.sum()
-    assert (delta[crossing] < 1e-3 * gp[crossing]).all()
-
-
 def test_hllc_consistency_and_upwinding():
     rng = np.random.Generator(np.random.PCG64(9))
     for _ in range(50):
