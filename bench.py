@@ -173,6 +173,49 @@ def cpu_baseline(seconds_hint=20.0):
                       f"(thread pools limited to 1; {busy:.2f} CPU-s per s measured)"}
 
 
+def host_cores():
+    """CPUs this process may run on (its affinity mask), capped at the
+    box's CPU share of one GPU (16)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(16, n))
+
+
+def cpu_worker(seconds_hint):
+    """One oracle instance of the CPU baseline's sample, run in a child
+    process (``--cpu-worker``): prints its step count and time as JSON."""
+    r = cpu_baseline(seconds_hint)
+    print(json.dumps({"rate": r["value"], "sample": r["sample"]}), flush=True)
+
+
+def cpu_baseline_all_cores(seconds_hint=20.0):
+    """The same oracle on every host core at once: one independent oracle
+    instance of the sample per core, each in its own child process with
+    one thread (the oracle has no parallel decomposition of one mesh; the
+    host's aggregate throughput on the workload is the sum of the
+    instances' rates over the same window)."""
+    import subprocess
+    n = host_cores()
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    procs = [subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker",
+                               str(seconds_hint)], stdout=subprocess.PIPE, env=env, text=True)
+             for _ in range(n)]
+    rates = []
+    for pr in procs:
+        out, _ = pr.communicate()
+        if pr.returncode != 0:
+            raise RuntimeError(f"cpu baseline worker failed with status {pr.returncode}")
+        rates.append(json.loads(out.strip().splitlines()[-1])["rate"])
+    return {"value": float(sum(rates)), "unit": "cell-stage updates/s", "cores": n,
+            "kind": "oracle",
+            "sample": f"{n} concurrent single-thread processes, each the oracle rk3 on the "
+                      f"24576-cell mixed mesh (128x128 squares, 64x64 checkerboard, 30% "
+                      f"jitter) for about {seconds_hint:.0f} s; value = sum of their rates "
+                      f"(per process {min(rates):.3g} to {max(rates):.3g})"}
+
+
 def run_batch(args):
     """The 256-instance batch: every instance advanced by the same graph-
     captured launches, each with its own CFL time step.  Prints one JSON
@@ -210,14 +253,23 @@ def run_batch(args):
     el = time.perf_counter() - s0
     B.check()
     err = None
+    fp64 = None
     if not args.no_check and prec == uw.UW_FP32:
         ph64 = uw.make_physics(uw.UW_EULER, 1.0, 1.0, 1.4, uw.UW_FP64)
         B64 = uw.Batch(Ms, ph64)
+        B64.autotune(ph64)
         W64 = torch.from_numpy(W0).to(dev)
         t64 = torch.zeros(256, dtype=torch.float64, device=dev)
-        for _ in range(args.warmup + args.steps):
+        for _ in range(args.warmup):
             B64.rk3_step(W64, t64, cfl=0.5, n_steps=1)
         torch.cuda.synchronize()
+        s64 = time.perf_counter()
+        for _ in range(args.steps):
+            B64.rk3_step(W64, t64, cfl=0.5, n_steps=1)
+        torch.cuda.synchronize()
+        el64 = time.perf_counter() - s64
+        B64.check()
+        fp64 = {"value": ncell * 3 * args.steps / el64, "ms_per_step": el64 / args.steps * 1e3}
         a = B.to_original(W.cpu().numpy())
         b = B64.to_original(W64.cpu().numpy())
         errs = [l1_errors(x, y) for x, y in zip(a, b)]
@@ -241,6 +293,10 @@ def run_batch(args):
         "stage": {"algorithmic_bytes": sbytes, "ms": stage_s * 1e3,
                   "achieved_GBs": sbytes / stage_s / 1e9,
                   "hbm_frac": sbytes / stage_s / 1e9 / PEAK_HBM_GBS},
+        "hbm_roofline_frac": sbytes / stage_s / 1e9 / PEAK_HBM_GBS,
+        "fp64_value": None if fp64 is None else fp64["value"],
+        "fp64_ms_per_step": None if fp64 is None else fp64["ms_per_step"],
+        "host_cores": host_cores(),
         "fp32_vs_fp64_rel_l1": None if err is None else err["max_over_variables"],
         "fp32_vs_fp64_rel_l1_detail": err,
         "cpu_baseline": None,
@@ -261,7 +317,11 @@ def main():
     ap.add_argument("--no-check", action="store_true", help="skip the FP64 reference run")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (calibrates HBM byte counters)")
+    ap.add_argument("--cpu-worker", type=float, default=None, help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker is not None:
+        cpu_worker(args.cpu_worker)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): the library runs each "
               "mesh on a single device and has no multi-GPU decomposition.", file=sys.stderr)
@@ -306,23 +366,38 @@ def main():
     t1 = time.perf_counter()
     M.autotune(phys)
     log(f"autotune {time.perf_counter() - t1:.1f} s; schedule {M.schedule()}")
+    def timed_steps(ph, Wd, td):
+        # each call replays the captured graph of one step
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        for _ in range(args.steps):
+            M.rk3_step(ph, Wd, td, cfl=0.5)
+        torch.cuda.synchronize()
+        return time.perf_counter() - a
+
     for _ in range(args.warmup):
         M.rk3_step(phys, W, t, cfl=0.5)
     torch.cuda.synchronize()
     M.check()
+    el = timed_steps(phys, W, t)
+    M.check()
+    # the same number of steps again, launched one kernel at a time with HIP
+    # events on the library's stream around each launch: per-kernel times
     M.profile(enable=1)
     torch.cuda.synchronize()
     s0 = time.perf_counter()
     for k in range(args.steps):
         M.rk3_step(phys, W, t, cfl=0.5)
     torch.cuda.synchronize()
-    el = time.perf_counter() - s0
+    el_prof = time.perf_counter() - s0
     (rms, fms), (rn, fn) = M.profile(enable=0)
     M.check()
-    log(f"timed {args.steps} steps in {el:.3f} s; recon {rms / max(rn, 1):.3f} ms x {rn}, "
+    log(f"timed {args.steps} steps in {el:.3f} s (graph replays); per-kernel pass "
+        f"{el_prof:.3f} s: recon {rms / max(rn, 1):.3f} ms x {rn}, "
         f"flux {fms / max(fn, 1):.3f} ms x {fn}")
 
     N, Nq = M.n_cells, M.n_quads
+    N_cells = N
     p = 4 if prec == uw.UW_FP32 else 8
     value = N * 3 * args.steps / el
     rbytes = Nq * recon_bytes(4, p, nvar) + (N - Nq) * recon_bytes(3, p, nvar)
@@ -333,25 +408,39 @@ def main():
     sbytes = Nq * stage_bytes(4, p, nvar) + (N - Nq) * stage_bytes(3, p, nvar)
 
     err = None
+    fp64 = None
     if not args.no_check and prec == uw.UW_FP32:
-        # the same steps in FP64 on the device: the FP32 result's error
+        # the same steps in FP64 on the device: its throughput (timed like
+        # the FP32 steps) and the FP32 result's error against it
         W64 = torch.from_numpy(W0i).to(dev)
         t64 = torch.zeros(1, dtype=torch.float64, device=dev)
         ph64 = uw.make_physics(eq, 1.0, 1.0, 1.4, uw.UW_FP64)
-        for _ in range(args.warmup + args.steps):
+        for _ in range(args.warmup):
+            M.rk3_step(ph64, W64, t64, cfl=0.5)
+        el64 = timed_steps(ph64, W64, t64)
+        for _ in range(args.steps):
             M.rk3_step(ph64, W64, t64, cfl=0.5)
         torch.cuda.synchronize()
+        M.check()
+        fp64 = {"value": N_cells * 3 * args.steps / el64, "ms_per_step": el64 / args.steps * 1e3}
         a = W.cpu().numpy()
         b = W64.cpu().numpy()
         err = l1_errors(a, b)
-        log(f"fp32 vs fp64 relative L1 after {args.warmup + args.steps} steps: {err}")
+        log(f"fp64: {fp64['value']:.3g} cell-stage/s; fp32 vs fp64 relative L1 after "
+            f"{args.warmup + 2 * args.steps} steps: {err}")
         del W64
 
     base = None
     if not args.no_cpu_baseline:
         t1 = time.perf_counter()
-        base = cpu_baseline()
-        log(f"cpu baseline {base['value']:.3g} cell-stage/s ({time.perf_counter() - t1:.1f} s)")
+        single = cpu_baseline()
+        log(f"cpu baseline, one core: {single['value']:.3g} cell-stage/s "
+            f"({time.perf_counter() - t1:.1f} s)")
+        t1 = time.perf_counter()
+        base = cpu_baseline_all_cores()
+        base["one_core"] = {"value": single["value"], "cores": 1, "sample": single["sample"]}
+        log(f"cpu baseline, {base['cores']} cores: {base['value']:.3g} cell-stage/s "
+            f"({time.perf_counter() - t1:.1f} s)")
 
     traffic = committed_traffic()
     out = {
@@ -381,11 +470,18 @@ def main():
                      "frac_of_published": achieved / PEAK_FP32_PUBLISHED,
                      "hbm": {"algorithmic_bytes": rbytes, "achieved_GBs": hbm_achieved,
                              "frac": hbm_achieved / PEAK_HBM_GBS}},
+        "hbm_roofline_frac": sbytes / (el / args.steps / 3) / 1e9 / PEAK_HBM_GBS,
         "schedule": M.schedule(),
         "stage": {"algorithmic_bytes": sbytes, "ms": el / args.steps / 3 * 1e3,
                   "achieved_GBs": sbytes / (el / args.steps / 3) / 1e9,
                   "hbm_frac": sbytes / (el / args.steps / 3) / 1e9 / PEAK_HBM_GBS,
-                  "recon_ms": ravg * 1e3, "flux_ms": fms / max(fn, 1)},
+                  "recon_ms": ravg * 1e3, "flux_ms": fms / max(fn, 1),
+                  "timing": "value: graph replays of whole steps; per-kernel times: a second "
+                            "pass of as many steps launched one kernel at a time with HIP events",
+                  "per_kernel_pass_ms_per_step": el_prof / args.steps * 1e3},
+        "fp64_value": None if fp64 is None else fp64["value"],
+        "fp64_ms_per_step": None if fp64 is None else fp64["ms_per_step"],
+        "host_cores": host_cores(),
         "fp32_vs_fp64_rel_l1": None if err is None else err["max_over_variables"],
         "fp32_vs_fp64_rel_l1_detail": err,
         "cpu_baseline": base,

@@ -16,6 +16,22 @@ def rel_l1(a, b):
     return float((num / den).max())
 
 
+def max_rel(a, b):
+    """Largest over variables of max|a - b| / max|b|: an element-by-element
+    bar (one bad element fails it, however many good ones surround it)."""
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    num = np.abs(a - b).max(axis=-1)
+    den = np.maximum(np.abs(b).max(axis=-1), 1e-300)
+    return float((num / den).max())
+
+
+def parity_err(a, b):
+    """The larger of the relative L1 difference and the element-wise one
+    (max_rel): parity tests hold both to the same bar."""
+    return max(rel_l1(a, b), max_rel(a, b))
+
+
 def physics_for(uw, equation, precision):
     eq = uw.UW_EULER if equation == "euler" else uw.UW_ADVECTION
     pr = uw.UW_FP64 if precision == "fp64" else uw.UW_FP32
