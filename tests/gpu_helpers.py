@@ -26,10 +26,24 @@ def max_rel(a, b):
     return float((num / den).max())
 
 
-def parity_err(a, b):
-    """The larger of the relative L1 difference and the element-wise one
-    (max_rel): parity tests hold both to the same bar."""
-    return max(rel_l1(a, b), max_rel(a, b))
+# Element-wise bar of the FP64 comparisons: the FP64 linear weights are
+# fixed by ill-conditioned least-squares solves (Sec. 3.3), and the library's
+# solve (one-sided Jacobi SVD) and the oracle's (LAPACK SVD) agree only to
+# about 1e-10 of the largest weight on 30%-jittered meshes
+# (test_fp64_tables_match_oracle); where a weight that differs that much
+# multiplies a large candidate increment, one residual element moves by up
+# to about 1e-11 of the largest.  FP32 rounding dominates that in the FP32
+# comparisons, which keep their L1 bar element by element.
+FP64_ELEMENT_FACTOR = 100.0
+
+
+def parity_err(a, b, tol):
+    """Relative error in units of the relative-L1 bar ``tol``: the larger of
+    the relative L1 difference and the element-wise one (max_rel), the latter
+    scaled so that it meets the same ``<= tol`` test at its own bar (tol
+    itself for FP32 bars, FP64_ELEMENT_FACTOR x tol for FP64 ones)."""
+    elem_tol = FP64_ELEMENT_FACTOR * tol if tol <= 1e-12 else tol
+    return max(rel_l1(a, b), max_rel(a, b) * (tol / elem_tol))
 
 
 def physics_for(uw, equation, precision):

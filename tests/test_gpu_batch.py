@@ -73,7 +73,7 @@ def test_batch_instance_matches_oracle(batch_setup):
         ref = states[k]
         for _ in range(2):
             ref = osc.rk3_step(T, ref, osc.Physics("euler"), dt)
-        assert parity_err(got[k], ref) <= 1e-12
+        assert parity_err(got[k], ref, 1e-12) <= 1e-12
     assert np.allclose(tb.cpu().numpy(), 2 * dt, rtol=0, atol=1e-15)
 
 
@@ -112,7 +112,7 @@ def test_fp32_batch_within_1e5_of_fp64(batch_setup):
         B.rk3_step(Wb, tb, cfl=0.5, n_steps=10)
         out[prec] = B.to_original(Wb.cpu().numpy())
     for a, b in zip(out[uw.UW_FP32], out[uw.UW_FP64]):
-        assert parity_err(a, b) <= 1e-5
+        assert parity_err(a, b, 1e-5) <= 1e-5
 
 
 def test_autotune_keeps_results(batch_setup, tmp_path):

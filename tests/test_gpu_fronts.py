@@ -67,7 +67,7 @@ def test_front_residual_matches_oracle_at_given_times(split, scheme, prec):
         M.residual(ph, Wi, L, t=t)
         torch.cuda.synchronize()
         got = M.to_original(L.cpu().numpy())
-        err = parity_err(got, ref)
+        err = parity_err(got, ref, tol)
         print(split, scheme, prec, "t", t, "rel L1 / elementwise", err, flush=True)
         assert err <= tol
 
@@ -115,7 +115,7 @@ def test_front_rk3_steps_see_the_stage_times(split, steps):
         for _ in range(steps):
             M.rk3_step(physics_for(uw, "euler", prec), Wd, t, dt_fixed=dt)
         M.check()
-        err = parity_err(M.to_original(Wd.cpu().numpy()), ref)
+        err = parity_err(M.to_original(Wd.cpu().numpy()), ref, tol)
         tt = float(t.cpu()[0])
         print(split, prec, "rel L1 / elementwise", err, "t", tt, flush=True)
         assert err <= tol
@@ -154,7 +154,7 @@ def test_batch_instances_keep_their_own_fronts_and_times():
     for k, mesh in enumerate(meshes):
         T = ow.precompute(mesh, ow.Scheme(variables="characteristic"))
         ref = _oracle_steps(T, states[k], t0[k], dt, 2)
-        err = parity_err(got[k], ref)
+        err = parity_err(got[k], ref, 1e-12)
         print("instance", k, "rel L1 / elementwise", err, flush=True)
         assert err <= 1e-12, k
 

@@ -72,9 +72,9 @@ def _check(uw, mesh, W, samples, dt, schedules=("tune",)):
     M.precompute()
     ref = op.rk3_at(mesh, W, samples, osc.Physics("euler"), dt)
     got64 = _gpu_step(uw, M, W, "fp64", dt)
-    e64 = parity_err(got64[:, samples], ref)
+    e64 = parity_err(got64[:, samples], ref, 1e-12)
     got32 = _gpu_step(uw, M, W, "fp32", dt)
-    e32 = parity_err(got32[:, samples], ref)
+    e32 = parity_err(got32[:, samples], ref, 1e-5)
     print(f"{mesh.name}: {mesh.n_cells} cells, {len(samples)} samples, "
           f"fp64 rel err {e64:.3e}, fp32 rel err {e32:.3e}", flush=True)
     assert e64 <= 1e-12
@@ -169,7 +169,7 @@ def test_batch_256_instances():
         del Wb
     got = {p: np.concatenate([out[p][k][:, refs[k][0]] for k in refs], 1) for p in out}
     ref = np.concatenate([refs[k][1] for k in refs], 1)
-    e64, e32 = parity_err(got["fp64"], ref), parity_err(got["fp32"], ref)
+    e64, e32 = parity_err(got["fp64"], ref, 1e-12), parity_err(got["fp32"], ref, 1e-5)
     print(f"batch of 256 ({sum(m.n_cells for m in meshes)} cells): fp64 {e64:.3e}, "
           f"fp32 {e32:.3e}", flush=True)
     assert e64 <= 1e-12
