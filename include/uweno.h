@@ -206,6 +206,29 @@ uw_status uw_mesh_table(const uw_mesh* mesh, int32_t which, double* out);
 uw_status uw_residual(uw_mesh* mesh, const uw_physics* physics, const double* W, double* L,
                       void* stream);
 
+/* uw_residual for callers that cannot allocate device memory: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * It computes the same L(W) with the same kernels (bit for bit equal to
+ * uw_residual) and calls no hipMalloc, hipFree or other allocating routine.
+ * W, L: device FP64 [V][n_cells] (internal order), as for uw_residual;
+ * owned by the caller.  Preconditions (else UW_ESTATE, nothing launched):
+ * the mesh is precomputed and its device tables in physics->precision
+ * exist, i.e. an earlier uw_residual, uw_residual_at, uw_rk3_step,
+ * uw_cfl_dt or uw_autotune call in that precision ran on this mesh.
+ * Scratch: the Gauss-point face states live in one fixed 64 MiB device
+ * array per GPU, held from the library's load until the process ends;
+ * n_cells * 8 * V * (4 in FP32, 8 in FP64) bytes must fit, i.e. at most
+ * 524288 cells for FP32 Euler, 262144 for FP64 Euler, 2097152 and 1048576
+ * for scalar advection; a larger mesh gets UW_EINVAL before any launch.
+ * Every call on one GPU uses that GPU's array: calls whose execution
+ * overlaps on the device (different streams, concurrent host threads)
+ * race and give wrong results; calls ordered on one stream are safe.  No
+ * value of the array needs to start at zero: each call writes every face
+ * state it reads.  Device-side failures set the mesh's error flag
+ * (uw_check).  Errors: UW_EINVAL, UW_ESTATE, UW_EDEVICE. */
+uw_status uw_residual_noalloc(uw_mesh* mesh, const uw_physics* physics, const double* W,
+                              double* L, void* stream);
+
 /* uw_residual at time t (host value): only moving-front faces depend on
  * it; uw_residual is this call at t = 0. */
 uw_status uw_residual_at(uw_mesh* mesh, const uw_physics* physics, const double* W, double* L,

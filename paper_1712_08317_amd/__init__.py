@@ -75,7 +75,8 @@ class DiagC(ctypes.Structure):
 
 
 EXPORTS = ["uw_last_error", "uw_mesh_upload", "uw_mesh_info", "uw_mesh_export",
-           "uw_precompute_geometry", "uw_mesh_table", "uw_residual", "uw_residual_at", "uw_rk3_step",
+           "uw_precompute_geometry", "uw_mesh_table", "uw_residual", "uw_residual_at",
+           "uw_residual_noalloc", "uw_rk3_step",
            "uw_cfl_dt",
            "uw_batch_create", "uw_batch_offsets", "uw_batch_rk3_step", "uw_autotune", "uw_check",
            "uw_profile", "uw_schedule", "uw_mesh_destroy", "uw_batch_destroy"]
@@ -98,6 +99,7 @@ def _load():
         "uw_mesh_table": (i32, [vp, i32, vp]),
         "uw_residual": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, vp]),
         "uw_residual_at": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, dbl, vp]),
+        "uw_residual_noalloc": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, vp]),
         "uw_rk3_step": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, dbl, dbl, vp, vp]),
         "uw_cfl_dt": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, vp, vp]),
         "uw_batch_create": (i32, [vp, i32, ctypes.POINTER(PhysicsC), ctypes.POINTER(vp)]),
@@ -276,6 +278,14 @@ class Mesh:
         else:
             _check(LIB.uw_residual_at(self.handle, ctypes.byref(physics), _ptr(W), _ptr(L),
                                       float(t), _stream(stream)))
+
+    def residual_noalloc(self, physics: PhysicsC, W, L, stream=None):
+        """L = L(W) without any device allocation (face states in the
+        library's fixed per-device scratch; meshes up to 524288 cells in
+        FP32 Euler); needs one earlier residual in the same precision."""
+        self._check_state(physics, W=W, L=L)
+        _check(LIB.uw_residual_noalloc(self.handle, ctypes.byref(physics), _ptr(W), _ptr(L),
+                                       _stream(stream)))
 
     def rk3_step(self, physics: PhysicsC, W, t_dev, cfl=0.5, dt_fixed=0.0, t_end=float("inf"),
                  stream=None):

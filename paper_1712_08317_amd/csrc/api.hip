@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <tuple>
@@ -475,13 +476,15 @@ hipError_t ev_begin(Engine& E, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
   return hipEventRecord(*a, st);
 }
 
-// One residual evaluation (mode 0) or RK stage (modes 1..3).
+// One residual evaluation (mode 0) or RK stage (modes 1..3), with the face
+// states in FS (the engine's buffer unless given).
 template <class T>
 uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, const double* Wn,
-                double* W_out, const uw::StageTime& tm, hipStream_t st, bool timed) {
+                double* W_out, const uw::StageTime& tm, hipStream_t st, bool timed,
+                T* FS = nullptr) {
   const int nvar = nvar_of(p);
   DevTables<T>& d = tables_of<T>(E);
-  T* FS = E.FS.template as<T>();
+  if (!FS) FS = E.FS.template as<T>();
   const bool prof = timed && E.profiling;
   hipEvent_t a = nullptr, b = nullptr;
   if (prof) UW_HIP(ev_begin(E, st, &a, &b));
@@ -564,6 +567,51 @@ uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, doubl
   }
   UW_HIP(hipGraphLaunch(it->second, st));
   return UW_OK;
+}
+
+// Face states of uw_residual_noalloc: one fixed array per device, never
+// allocated or freed by the library.  In host code `scratch` names a host
+// stand-in; its device address on each GPU comes from hipGetSymbolAddress,
+// taken once per device with that device current and kept in scratch_dev.
+constexpr size_t kNoAllocScratch = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratch];
+
+std::mutex g_scratch_mu;
+void* g_scratch_dev[64] = {};
+
+// Device address of `scratch` on `device`, which must be the current device.
+uw_status scratch_on(int device, void** out) {
+  if (device < 0 || device >= 64) return fail(UW_EINVAL, "device index out of range (0..63)");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[device]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+    if (!ptr) return fail(UW_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    g_scratch_dev[device] = ptr;
+  }
+  *out = g_scratch_dev[device];
+  return UW_OK;
+}
+
+template <class T>
+uw_status residual_noalloc(Engine& E, const uw_physics* p, const double* W, double* L,
+                           hipStream_t st) {
+  if (!tables_of<T>(E).ready || !E.flag.p)
+    return fail(UW_ESTATE,
+                "uw_residual_noalloc: the mesh's device tables in this precision do not exist "
+                "yet; call uw_residual (or uw_rk3_step, uw_cfl_dt, uw_autotune) once in this "
+                "precision first");
+  const int64_t N = E.staged.N;
+  const size_t need = (size_t)N * 8 * (size_t)nvar_of(p) * sizeof(T);
+  if (need > kNoAllocScratch)
+    return fail(UW_EINVAL, "uw_residual_noalloc: " + std::to_string(N) + " cells need " +
+                               std::to_string(need) + " bytes of face-state scratch; the limit "
+                               "is " + std::to_string(kNoAllocScratch) + " bytes");
+  void* ptr = nullptr;
+  UW_TRY(scratch_on(E.device, &ptr));
+  return stage<T>(E, p, 0, W, W, L, uw::StageTime{nullptr, nullptr, 0.0, 0.0}, st, false,
+                  static_cast<T*>(ptr));
 }
 
 uw_status check_scheme(const uw_scheme* sc) {
@@ -777,6 +825,22 @@ uw_status uw_residual_at(uw_mesh* m, const uw_physics* p, const double* W, doubl
 
 uw_status uw_residual(uw_mesh* m, const uw_physics* p, const double* W, double* L, void* stream) {
   return uw_residual_at(m, p, W, L, 0.0, stream);
+}
+
+uw_status uw_residual_noalloc(uw_mesh* m, const uw_physics* p, const double* W, double* L,
+                              void* stream) {
+  g_err.clear();
+  if (!m || !W || !L) return fail(UW_EINVAL, "mesh, W and L must not be NULL");
+  UW_TRY(check_physics(p));
+  if (!m->precomputed) return fail(UW_ESTATE, "call uw_precompute_geometry first");
+  if (m->eng.device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
+  if (!m->eng.staged_ready)
+    return fail(UW_ESTATE, "uw_residual_noalloc: the mesh's device tables do not exist yet; call "
+                           "uw_residual once in this precision first");
+  UW_HIP(hipSetDevice(m->eng.device));
+  hipStream_t st = (hipStream_t)stream;
+  if (p->precision == UW_FP64) return residual_noalloc<double>(m->eng, p, W, L, st);
+  return residual_noalloc<float>(m->eng, p, W, L, st);
 }
 
 uw_status uw_rk3_step(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,

@@ -127,9 +127,15 @@ def test_call_order_and_arguments(uw):
     with pytest.raises(uw.UwError) as e:        # host-only mesh
         M.residual(ph, W, W, stream=0)
     assert e.value.status == uw.UW_ESTATE
+    with pytest.raises(uw.UwError) as e:        # host-only mesh, no-allocation variant
+        M.residual_noalloc(ph, W, W, stream=0)
+    assert e.value.status == uw.UW_ESTATE
     bad = uw.make_physics(equation=7)
     with pytest.raises(uw.UwError) as e:
         M.residual(bad, W, W, stream=0)
+    assert e.value.status == uw.UW_EINVAL
+    with pytest.raises(uw.UwError) as e:
+        M.residual_noalloc(bad, W, W, stream=0)
     assert e.value.status == uw.UW_EINVAL
     st = uw.LIB.uw_mesh_upload(None, -1, None)
     assert st == uw.UW_EINVAL
