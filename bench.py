@@ -290,6 +290,7 @@ def run_batch(args):
                    "rk3_steps": args.steps, "cfl": 0.5, "graph": "one captured step per replay"},
         "roofline": None,
         "schedule": B.schedule(),
+        "tile": B.tile_size(),
         "stage": {"algorithmic_bytes": sbytes, "ms": stage_s * 1e3,
                   "achieved_GBs": sbytes / stage_s / 1e9,
                   "hbm_frac": sbytes / stage_s / 1e9 / PEAK_HBM_GBS},
@@ -365,7 +366,9 @@ def main():
         del a, b
     t1 = time.perf_counter()
     M.autotune(phys)
-    log(f"autotune {time.perf_counter() - t1:.1f} s; schedule {M.schedule()}")
+    tile = M.tile_size()
+    sched = M.schedule()
+    log(f"autotune {time.perf_counter() - t1:.1f} s; tile {tile}, schedule {sched}")
     def timed_steps(ph, Wd, td):
         # each call replays the captured graph of one step
         torch.cuda.synchronize()
@@ -415,6 +418,7 @@ def main():
         W64 = torch.from_numpy(W0i).to(dev)
         t64 = torch.zeros(1, dtype=torch.float64, device=dev)
         ph64 = uw.make_physics(eq, 1.0, 1.0, 1.4, uw.UW_FP64)
+        M.autotune(ph64)          # FP64 stages use 256-cell tiles
         for _ in range(args.warmup):
             M.rk3_step(ph64, W64, t64, cfl=0.5)
         el64 = timed_steps(ph64, W64, t64)
@@ -471,7 +475,8 @@ def main():
                      "hbm": {"algorithmic_bytes": rbytes, "achieved_GBs": hbm_achieved,
                              "frac": hbm_achieved / PEAK_HBM_GBS}},
         "hbm_roofline_frac": sbytes / (el / args.steps / 3) / 1e9 / PEAK_HBM_GBS,
-        "schedule": M.schedule(),
+        "schedule": sched,
+        "tile": tile,
         "stage": {"algorithmic_bytes": sbytes, "ms": el / args.steps / 3 * 1e3,
                   "achieved_GBs": sbytes / (el / args.steps / 3) / 1e9,
                   "hbm_frac": sbytes / (el / args.steps / 3) / 1e9 / PEAK_HBM_GBS,

@@ -252,8 +252,8 @@ uw_status uw_cfl_dt(uw_mesh* mesh, const uw_physics* physics, const double* W, d
                     double* dt_dev, void* stream);
 
 /* Many independent meshes advanced together.  Every RK stage is one
- * persistent reconstruction launch per cell type over the 256-cell tiles of
- * all instances plus one flux launch; the steps of uw_batch_rk3_step are
+ * persistent reconstruction launch per cell type over the tiles of all
+ * instances plus one flux launch; the steps of uw_batch_rk3_step are
  * captured once into a hipGraph and replayed.  Every mesh must be
  * precomputed with the same scheme and live on one device; the batch copies
  * their tables (the meshes may be destroyed afterwards).
@@ -276,11 +276,12 @@ uw_status uw_batch_offsets(const uw_batch* batch, int64_t* cell_offsets);
 uw_status uw_batch_rk3_step(uw_batch* batch, double* W, double cfl, double dt_fixed,
                             double t_end, int32_t n_steps, double* t_dev, void* stream);
 
-/* Chooses the launch schedule (number of persistent blocks of the
- * reconstruction kernels of each cell type and of the flux kernel: one
- * block per 256-cell tile, or 1, 2, 4 or 8 blocks per compute unit) by
- * timing residual evaluations on the mesh or batch (exactly one of them)
- * and stores it there.  `cache_path` (nullable): a text file of earlier
+/* Chooses the tile size (256 or 512 cells; 512 only for FP32 WENO on the
+ * conserved variables) and the launch schedule (number of persistent blocks
+ * of the reconstruction kernels of each cell type and of the flux kernel:
+ * one block per tile, or 1, 2, 4 or 8 blocks per compute unit) by timing
+ * residual evaluations on the mesh or batch (exactly one of them) and
+ * stores both there.  `cache_path` (nullable): a text file of earlier
  * choices keyed by the workload's shape, read first and appended to. */
 uw_status uw_autotune(uw_mesh* mesh, uw_batch* batch, const uw_physics* physics,
                       const char* cache_path, void* stream);
@@ -288,8 +289,19 @@ uw_status uw_autotune(uw_mesh* mesh, uw_batch* batch, const uw_physics* physics,
 /* Reads (get, nullable, host [3]) and/or sets (set, nullable) the launch
  * schedule of a mesh or batch (exactly one): persistent blocks of the
  * quadrilateral reconstruction, of the triangle reconstruction and of the
- * flux kernel; 0 = one block per 256-cell tile.  Set is applied before get. */
+ * flux kernel; 0 = one block per tile.  Set is applied before get. */
 uw_status uw_schedule(uw_mesh* mesh, uw_batch* batch, int32_t* get, const int32_t* set);
+
+/* Tile size of a mesh or batch (exactly one): cells per tile, i.e. threads
+ * per reconstruction and flux block, and the unit of LDS staging.  set =
+ * 256 or 512 changes it (0 leaves it): the staging lists are rebuilt on the
+ * host, the device tables are dropped after the device has finished queued
+ * work (uploaded again on first use) and captured steps are retired.  512
+ * serves FP32 WENO on the conserved variables only; other evaluations
+ * then return UW_EINVAL.  get (nullable, host) receives the current size.
+ * Default 256.  Errors: UW_EINVAL (size not 256 or 512), UW_EDEVICE,
+ * UW_ENOMEM. */
+uw_status uw_tile_size(uw_mesh* mesh, uw_batch* batch, int32_t set, int32_t* get);
 
 /* Launch timing (tracing): with enable = 1 every later reconstruction and
  * flux launch of this mesh is bracketed by HIP events on the caller's

@@ -79,7 +79,7 @@ EXPORTS = ["uw_last_error", "uw_mesh_upload", "uw_mesh_info", "uw_mesh_export",
            "uw_residual_noalloc", "uw_rk3_step",
            "uw_cfl_dt",
            "uw_batch_create", "uw_batch_offsets", "uw_batch_rk3_step", "uw_autotune", "uw_check",
-           "uw_profile", "uw_schedule", "uw_mesh_destroy", "uw_batch_destroy"]
+           "uw_profile", "uw_schedule", "uw_tile_size", "uw_mesh_destroy", "uw_batch_destroy"]
 
 
 def _load():
@@ -109,6 +109,7 @@ def _load():
         "uw_check": (i32, [vp, vp, vp]),
         "uw_profile": (i32, [vp, i32, vp, vp]),
         "uw_schedule": (i32, [vp, vp, vp, vp]),
+        "uw_tile_size": (i32, [vp, vp, i32, vp]),
         "uw_mesh_destroy": (None, [vp]),
         "uw_batch_destroy": (None, [vp]),
     }
@@ -315,6 +316,12 @@ class Mesh:
                                None if s is None else s.ctypes.data))
         return tuple(int(x) for x in got)
 
+    def tile_size(self, set_to=0):
+        """Cells per tile (256 or 512); ``set_to`` changes it first."""
+        got = ctypes.c_int32(0)
+        _check(LIB.uw_tile_size(self.handle, None, int(set_to), ctypes.byref(got)))
+        return got.value
+
     def profile(self, enable=-1):
         """Returns ((recon_ms, flux_ms), (recon_count, flux_count)) recorded
         so far and clears them; enable = 1/0 switches recording on/off."""
@@ -370,6 +377,12 @@ class Batch:
         _check(LIB.uw_schedule(None, self.handle, got.ctypes.data,
                                None if s is None else s.ctypes.data))
         return tuple(int(x) for x in got)
+
+    def tile_size(self, set_to=0):
+        """As Mesh.tile_size, for the batch."""
+        got = ctypes.c_int32(0)
+        _check(LIB.uw_tile_size(None, self.handle, int(set_to), ctypes.byref(got)))
+        return got.value
 
     def autotune(self, physics: PhysicsC, cache_path=None, stream=None):
         _check(LIB.uw_autotune(None, self.handle, ctypes.byref(physics),

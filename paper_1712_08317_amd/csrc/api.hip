@@ -18,7 +18,6 @@
 #include "uw_device.h"
 #include "uw_host.h"
 
-static_assert(uw::kTile == uw::kTileCells, "host tile size and device block size differ");
 
 namespace {
 
@@ -136,6 +135,11 @@ void face_tables(const std::vector<double>& fgeo, const std::vector<int32_t>& fn
 struct Staged {
   int64_t N = 0;
   int32_t n_inst = 0, n_tq = 0, n_tt = 0, max_len_q = 0, max_len_t = 0;
+  int32_t tile = uw::kTile;     // cells per tile of the lists below
+  // per type: the cell each stencil slot s >= 1 reads ([S-1][rows], batch
+  // ids), and per instance its first row and first cell of that type
+  std::vector<int32_t> q_sid, t_sid;
+  std::vector<int64_t> q_row0, t_row0, q_first, t_first;   // [n_inst + 1] / [n_inst]
   std::vector<uw::Tile> tiles;
   std::vector<int32_t> tile_off, tile_ids, inst_tiles, fnb;
   std::vector<double> inflow;   // [n_states][4] prescribed states of all instances
@@ -168,11 +172,60 @@ void cat_type(const std::vector<const uw::HostTables*>& ts, bool quad, Get get, 
   }
 }
 
+// Tiles of `tile` consecutive cells of one type and one instance (all
+// quadrilateral tiles, then all triangle tiles, each by instance), their LDS
+// staging lists and slot positions.  Needs the sid tables and instance
+// ranges of S.
+void retile(Staged& S, int tile) {
+  const int n = S.n_inst;
+  const int threads = uw::default_threads();
+  S.tile = tile;
+  S.tiles.clear();
+  S.tile_ids.clear();
+  S.tile_off.assign(1, 0);
+  S.inst_tiles.assign(2 * (n + 1), 0);
+  S.max_len_q = S.max_len_t = 0;
+  for (int type = 0; type < 2; ++type) {
+    const bool q = type == 0;
+    const int Sn = q ? uw::kQuad.S : uw::kTri.S;
+    const int64_t R = q ? S.rows_q : S.rows_t;
+    std::vector<uint16_t>& lidx = q ? S.q_lidx : S.t_lidx;
+    lidx.assign((size_t)Sn * R, 0);
+    const std::vector<int32_t>& sid = q ? S.q_sid : S.t_sid;
+    int32_t count = 0;
+    std::vector<std::vector<int32_t>> lists;
+    for (int k = 0; k < n; ++k) {
+      const int64_t r0 = (q ? S.q_row0 : S.t_row0)[k];
+      const int64_t nk = (q ? S.q_row0 : S.t_row0)[k + 1] - r0;
+      const int64_t first = (q ? S.q_first : S.t_first)[k];
+      if (nk > 0)
+        uw::build_tile_lists(sid.data(), R, r0, nk, first, Sn, tile, threads, lidx.data(), lists);
+      else
+        lists.clear();
+      for (size_t j = 0; j < lists.size(); ++j) {
+        uw::Tile tl;
+        tl.first = (int32_t)(first + (int64_t)j * tile);
+        tl.row0 = (int32_t)(r0 + (int64_t)j * tile);
+        tl.count = (int32_t)std::min<int64_t>(tile, nk - (int64_t)j * tile);
+        tl.inst = k;
+        S.tiles.push_back(tl);
+        S.tile_ids.insert(S.tile_ids.end(), lists[j].begin(), lists[j].end());
+        S.tile_off.push_back((int32_t)S.tile_ids.size());
+        int32_t& mx = q ? S.max_len_q : S.max_len_t;
+        mx = std::max(mx, (int32_t)lists[j].size());
+      }
+      count += (int32_t)lists.size();
+      S.inst_tiles[type * (n + 1) + k + 1] = count;
+    }
+    (q ? S.n_tq : S.n_tt) = count;
+  }
+}
+
 // Concatenates per-mesh tables into the batch layout: cells of instance k
 // occupy [off_k, off_k + n_k); each type's table rows are concatenated by
 // instance; neighbour and staging ids are rebased.
 void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<const uw::HostTables*>& ts,
-              bool linear, Staged& S) {
+              bool linear, int tile, Staged& S) {
   const int n = (int)ms.size();
   S = Staged();
   S.n_inst = n;
@@ -185,40 +238,35 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
   S.N = off[n];
   S.rows_q = qrow[n];
   S.rows_t = trow[n];
-  // tiles and staging lists: quadrilateral tiles of every instance, then triangles
-  S.inst_tiles.assign(2 * (n + 1), 0);
-  S.tile_off.push_back(0);
-  for (int type = 0; type < 2; ++type) {
-    int32_t count = 0;
-    for (int k = 0; k < n; ++k) {
-      const uw::TypeTables& tt = type == 0 ? ts[k]->quad : ts[k]->tri;
-      const int64_t rows0 = type == 0 ? qrow[k] : trow[k];
-      const int64_t nt = (int64_t)tt.tile_off.size() - 1;
-      for (int64_t j = 0; j < nt; ++j) {
-        uw::Tile tl;
-        tl.first = (int32_t)(off[k] + tt.first + j * uw::kTile);
-        tl.row0 = (int32_t)(rows0 + j * uw::kTile);
-        tl.count = (int32_t)std::min<int64_t>(uw::kTile, tt.Nt - j * uw::kTile);
-        tl.inst = k;
-        S.tiles.push_back(tl);
-        for (int32_t q = tt.tile_off[j]; q < tt.tile_off[j + 1]; ++q)
-          S.tile_ids.push_back((int32_t)(tt.tile_ids[q] + off[k]));
-        S.tile_off.push_back((int32_t)S.tile_ids.size());
-      }
-      count += (int32_t)std::max<int64_t>(nt, 0);
-      S.inst_tiles[type * (n + 1) + k + 1] = count;
-      int32_t& mx = type == 0 ? S.max_len_q : S.max_len_t;
-      mx = std::max(mx, tt.max_tile_len);
-    }
-    (type == 0 ? S.n_tq : S.n_tt) = count;
+  // stencil slot cells per type (batch ids) and the instances' ranges
+  S.q_row0.assign(qrow.begin(), qrow.end());
+  S.t_row0.assign(trow.begin(), trow.end());
+  S.q_first.resize(n);
+  S.t_first.resize(n);
+  for (int k = 0; k < n; ++k) {
+    S.q_first[k] = off[k] + ts[k]->quad.first;
+    S.t_first[k] = off[k] + ts[k]->tri.first;
   }
+  for (int type = 0; type < 2; ++type) {
+    const bool q = type == 0;
+    const int64_t R = q ? S.rows_q : S.rows_t;
+    const int Sn = q ? uw::kQuad.S : uw::kTri.S;
+    std::vector<int32_t>& out = q ? S.q_sid : S.t_sid;
+    out.assign((size_t)(Sn - 1) * R, 0);
+    for (int k = 0; k < n; ++k) {
+      const uw::TypeTables& tt = q ? ts[k]->quad : ts[k]->tri;
+      const int64_t r0 = q ? qrow[k] : trow[k];
+      for (int s2 = 0; s2 < Sn - 1; ++s2)
+        for (int64_t r = 0; r < tt.Nt; ++r)
+          out[(size_t)s2 * R + r0 + r] = (int32_t)(tt.sid[(size_t)s2 * tt.Nt + r] + off[k]);
+    }
+  }
+  retile(S, tile);
   // per-type tables, structure of arrays with the batch row count
   for (int type = 0; type < 2; ++type) {
     const bool q = type == 0;
     const int64_t R = q ? S.rows_q : S.rows_t;
     const std::vector<int64_t>& ro = q ? qrow : trow;
-    cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<uint16_t>& { return t.lidx; },
-             R, ro, q ? S.q_lidx : S.t_lidx);
     cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.Y; }, R,
              ro, q ? S.q_Y : S.t_Y);
     cat_type(ts, q, [](const uw::TypeTables& t) -> const std::vector<double>& { return t.off; }, R,
@@ -289,6 +337,7 @@ struct Engine {
   DevTables<double> d64;
   DevTables<float> d32;
   DevBuf FS, Wtmp, dt, partial, flag;
+  int tile = uw::kTile;   // tile size asked for (the staged tables follow it)
   uw::Schedule sched;
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
@@ -383,6 +432,7 @@ uw_status ensure_tables(Engine& E) {
   uw::MeshDev<T>& v = d.view;
   v.N = S.N;
   v.n_inst = S.n_inst;
+  v.tile = S.tile;
   v.n_tq = S.n_tq;
   v.n_tt = S.n_tt;
   v.tiles = d.tiles.template as<uw::Tile>();
@@ -485,6 +535,10 @@ uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, co
   const int nvar = nvar_of(p);
   DevTables<T>& d = tables_of<T>(E);
   if (!FS) FS = E.FS.template as<T>();
+  if (E.staged.tile != 256 &&
+      (sizeof(T) == 8 || E.scheme.mode == 1 || (E.scheme.vars == 1 && nvar == 4)))
+    return fail(UW_EINVAL, "512-cell tiles serve FP32 WENO on the conserved variables only; "
+                           "set the tile size to 256 (uw_tile_size)");
   const bool prof = timed && E.profiling;
   hipEvent_t a = nullptr, b = nullptr;
   if (prof) UW_HIP(ev_begin(E, st, &a, &b));
@@ -614,6 +668,28 @@ uw_status residual_noalloc(Engine& E, const uw_physics* p, const double* W, doub
                   static_cast<T*>(ptr));
 }
 
+// Re-tiles a mesh's or batch's staged tables for `tile` cells per tile:
+// device tables are dropped (uploaded again on first use) after the device
+// has finished queued work, and captured steps are retired.
+uw_status set_tile(Engine& E, int tile) {
+  if (!uw::tile_size_ok(tile)) return fail(UW_EINVAL, "tile size must be 256 or 512");
+  if (tile == E.tile && (!E.staged_ready || E.staged.tile == tile)) return UW_OK;
+  if (E.device >= 0 && (E.d64.ready || E.d32.ready)) {
+    UW_HIP(hipSetDevice(E.device));
+    UW_HIP(hipDeviceSynchronize());
+  }
+  E.tile = tile;
+  E.reset_device();
+  if (E.staged_ready) {
+    try {
+      retile(E.staged, tile);
+    } catch (const std::bad_alloc&) {
+      E.staged_ready = false;
+      return fail(UW_ENOMEM, "host allocation while re-tiling");
+    }
+  }
+  return UW_OK;
+}
 uw_status check_scheme(const uw_scheme* sc) {
   if (!sc) return fail(UW_EINVAL, "scheme is NULL");
   if (!(sc->zeta >= 0.0) || !(sc->eps > 0.0) || !(sc->theta > 1.0) || !std::isfinite(sc->theta))
@@ -650,7 +726,7 @@ uw_status mesh_ready(uw_mesh* m) {
   if (m->eng.device < 0) return fail(UW_ESTATE, "mesh was uploaded host-only (device -1)");
   if (!m->eng.staged_ready) {
     try {
-      assemble({&m->host}, {&m->tables}, m->scheme.mode == 1, m->eng.staged);
+      assemble({&m->host}, {&m->tables}, m->scheme.mode == 1, m->eng.tile, m->eng.staged);
     } catch (const std::bad_alloc&) {
       return fail(UW_ENOMEM, "host allocation while staging tables");
     }
@@ -920,7 +996,7 @@ uw_status uw_batch_create(uw_mesh* const* meshes, int32_t n, const uw_physics* p
   b->eng.device = meshes[0]->eng.device;
   b->eng.scheme = meshes[0]->eng.scheme;
   try {
-    assemble(hm, ht, meshes[0]->scheme.mode == 1, b->eng.staged);
+    assemble(hm, ht, meshes[0]->scheme.mode == 1, b->eng.tile, b->eng.staged);
   } catch (const std::bad_alloc&) {
     delete b;
     return fail(UW_ENOMEM, "host allocation while staging the batch");
@@ -969,27 +1045,30 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[320];
       bool found = false;
+      int tile_found = uw::kTile;
       while (std::fgets(line, sizeof(line), f)) {
         long long a;
-        int c1, c2, c3, c4, c5, c6, rq, rt, fl;
-        if (std::sscanf(line, "%lld %d %d %d %d %d %d %d %d %d", &a, &c1, &c2, &c3, &c4, &c5, &c6,
-                        &rq, &rt, &fl) == 10) {
+        int c1, c2, c3, c4, c5, c6, rq, rt, fl, tl;
+        if (std::sscanf(line, "%lld %d %d %d %d %d %d %d %d %d %d", &a, &c1, &c2, &c3, &c4, &c5,
+                        &c6, &rq, &rt, &fl, &tl) == 11) {
           char k2[200];
           std::snprintf(k2, sizeof(k2), "%lld %d %d %d %d %d %d", a, c1, c2, c3, c4, c5, c6);
-          if (std::strcmp(k2, key) == 0 && rq >= 0 && rt >= 0 && fl >= 0) {
+          if (std::strcmp(k2, key) == 0 && rq >= 0 && rt >= 0 && fl >= 0 &&
+              uw::tile_size_ok(tl)) {
             E.sched = uw::Schedule{rq, rt, fl};
+            tile_found = tl;
             found = true;
           }
         }
       }
       std::fclose(f);
       if (found) {
+        UW_TRY(set_tile(E, tile_found));
         E.clear_graphs();
         return UW_OK;
       }
     }
   }
-  UW_TRY(p->precision == UW_FP64 ? prepare<double>(E, p) : prepare<float>(E, p));
   // a uniform admissible state to time the kernels on
   const int64_t N = E.staged.N;
   std::vector<double> h((size_t)nvar * N);
@@ -1011,38 +1090,80 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
   hipEvent_t e0, e1;
   UW_HIP(hipEventCreate(&e0));
   UW_HIP(hipEventCreate(&e1));
+  uw_status s = UW_OK;
+  // time of one residual evaluation (mean of three after a warm-up run)
+  auto time_residual = [&](float* out) -> uw_status {
+    float tot = 0.0f;
+    for (int rep = 0; rep < 4; ++rep) {
+      UW_HIP(hipEventRecord(e0, st));
+      UW_TRY(p->precision == UW_FP64
+                 ? stage<double>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(),
+                                 uw::StageTime{}, st, false)
+                 : stage<float>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(),
+                                uw::StageTime{}, st, false));
+      UW_HIP(hipEventRecord(e1, st));
+      UW_HIP(hipEventSynchronize(e1));
+      float ms = 0.0f;
+      UW_HIP(hipEventElapsedTime(&ms, e0, e1));
+      if (rep > 0) tot += ms;
+    }
+    *out = tot / 3.0f;
+    return UW_OK;
+  };
+  // tile sizes: 512 only where the kernels exist for it (FP32, WENO on the
+  // conserved variables) and its LDS fits
+  std::vector<int> tiles = {256};
+  if (p->precision == UW_FP32 && E.scheme.mode == 0 && !(E.scheme.vars == 1 && nvar == 4))
+    tiles.push_back(512);
   // candidate launch shapes: one block per tile (0) or k persistent blocks per CU
   const int mult[5] = {0, 1, 2, 4, 8};
-  uw_status s = UW_OK;
-  for (int knob = 0; knob < 3 && s == UW_OK; ++knob) {
-    int* val = knob == 0 ? &E.sched.recon_q : knob == 1 ? &E.sched.recon_t : &E.sched.flux;
-    int best_v = *val;
-    float best = 1e30f;
-    for (int c : mult) {
-      *val = c * cus;
-      float tot = 0.0f;
-      for (int rep = 0; rep < 4 && s == UW_OK; ++rep) {
-        hipError_t e = hipEventRecord(e0, st);
-        if (e == hipSuccess) {
-          s = p->precision == UW_FP64
-                  ? stage<double>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(),
-                                  uw::StageTime{}, st, false)
-                  : stage<float>(E, p, 0, Wt.as<double>(), Wt.as<double>(), Lt.as<double>(),
-                                 uw::StageTime{}, st, false);
-          if (s == UW_OK) e = hipEventRecord(e1, st);
-          if (s == UW_OK && e == hipSuccess) e = hipEventSynchronize(e1);
-          float ms = 0.0f;
-          if (s == UW_OK && e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-          if (rep > 0) tot += ms;
-        }
-        if (e != hipSuccess && s == UW_OK) s = hip_fail(e, "autotune timing");
-      }
-      if (s == UW_OK && tot < best) {
-        best = tot;
-        best_v = *val;
-      }
+  float best_all = 1e30f;
+  int best_tile = E.tile;
+  uw::Schedule best_sched = E.sched;
+  for (int tile : tiles) {
+    s = set_tile(E, tile);
+    if (s == UW_OK) s = p->precision == UW_FP64 ? prepare<double>(E, p) : prepare<float>(E, p);
+    if (s != UW_OK) break;
+    if (tile != 256) {
+      const size_t need =
+          std::max(p->precision == UW_FP64
+                       ? uw::recon_lds<double>(std::max(E.staged.max_len_q, E.staged.max_len_t),
+                                               nvar, tile)
+                       : uw::recon_lds<float>(std::max(E.staged.max_len_q, E.staged.max_len_t),
+                                              nvar, tile),
+                   (size_t)0);
+      int lim = 0;
+      UW_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, E.device));
+      if (need > (size_t)lim) continue;
     }
-    *val = best_v;
+    for (int knob = 0; knob < 3 && s == UW_OK; ++knob) {
+      int* val = knob == 0 ? &E.sched.recon_q : knob == 1 ? &E.sched.recon_t : &E.sched.flux;
+      int best_v = *val;
+      float best = 1e30f;
+      for (int c : mult) {
+        *val = c * cus;
+        float ms = 0.0f;
+        s = time_residual(&ms);
+        if (s != UW_OK) break;
+        if (ms < best) {
+          best = ms;
+          best_v = *val;
+        }
+      }
+      *val = best_v;
+    }
+    float ms = 0.0f;
+    if (s == UW_OK) s = time_residual(&ms);
+    if (s != UW_OK) break;
+    if (ms < best_all) {
+      best_all = ms;
+      best_tile = tile;
+      best_sched = E.sched;
+    }
+  }
+  if (s == UW_OK) {
+    s = set_tile(E, best_tile);
+    E.sched = best_sched;
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1050,10 +1171,20 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
   E.clear_graphs();
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "a")) {
-      std::fprintf(f, "%s %d %d %d\n", key, E.sched.recon_q, E.sched.recon_t, E.sched.flux);
+      std::fprintf(f, "%s %d %d %d %d\n", key, E.sched.recon_q, E.sched.recon_t, E.sched.flux,
+                   E.tile);
       std::fclose(f);
     }
   }
+  return UW_OK;
+}
+
+uw_status uw_tile_size(uw_mesh* m, uw_batch* b, int32_t set, int32_t* get) {
+  g_err.clear();
+  if ((!m) == (!b)) return fail(UW_EINVAL, "give exactly one of a mesh or a batch");
+  Engine& E = m ? m->eng : b->eng;
+  if (set != 0) UW_TRY(set_tile(E, set));
+  if (get) *get = E.tile;
   return UW_OK;
 }
 

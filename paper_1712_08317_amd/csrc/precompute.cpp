@@ -108,46 +108,37 @@ void precompute_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t,
   finish_tables(m, t, normal, length, threads);
 }
 
+void build_tile_lists(const int32_t* sid, int64_t stride, int64_t row0, int64_t n, int64_t first,
+                      int S, int tile, int threads, uint16_t* lidx,
+                      std::vector<std::vector<int32_t>>& lists) {
+  const int64_t nt = (n + tile - 1) / tile;
+  lists.assign(nt, {});
+  parallel_for(nt, threads, [&](int64_t s0, int64_t e0) {
+    std::vector<int32_t> ids;
+    for (int64_t k = s0; k < e0; ++k) {
+      const int64_t r0 = k * tile, r1 = std::min(n, r0 + tile);
+      ids.clear();
+      for (int64_t r = r0; r < r1; ++r) {
+        ids.push_back((int32_t)(first + r));
+        for (int s2 = 1; s2 < S; ++s2) ids.push_back(sid[(s2 - 1) * stride + row0 + r]);
+      }
+      std::sort(ids.begin(), ids.end());
+      ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
+      for (int64_t r = r0; r < r1; ++r)
+        for (int s2 = 0; s2 < S; ++s2) {
+          const int32_t id =
+              s2 == 0 ? (int32_t)(first + r) : sid[(s2 - 1) * stride + row0 + r];
+          lidx[s2 * stride + row0 + r] =
+              (uint16_t)(std::lower_bound(ids.begin(), ids.end(), id) - ids.begin());
+        }
+      lists[k] = ids;
+    }
+  });
+}
+
 void finish_tables(const HostMesh& m, HostTables& t, const std::vector<double>& normal,
                    const std::vector<double>& length, int threads) {
   const int64_t N = m.N;
-  // LDS staging lists of every tile of kTile consecutive cells
-  for (TypeTables* tt : {&t.quad, &t.tri}) {
-    const TypeConst& T = (tt == &t.quad) ? kQuad : kTri;
-    const int64_t n = tt->Nt, nt = (n + kTile - 1) / kTile;
-    std::vector<std::vector<int32_t>> lists(nt);
-    tt->lidx.assign((size_t)T.S * n, 0);
-    parallel_for(nt, threads, [&](int64_t s0, int64_t e0) {
-      std::vector<int32_t> ids;
-      for (int64_t tile = s0; tile < e0; ++tile) {
-        const int64_t r0 = tile * kTile, r1 = std::min(n, r0 + kTile);
-        ids.clear();
-        for (int64_t r = r0; r < r1; ++r) {
-          ids.push_back((int32_t)(tt->first + r));
-          for (int s2 = 1; s2 < T.S; ++s2) ids.push_back(tt->sid[(s2 - 1) * n + r]);
-        }
-        std::sort(ids.begin(), ids.end());
-        ids.erase(std::unique(ids.begin(), ids.end()), ids.end());
-        for (int64_t r = r0; r < r1; ++r)
-          for (int s2 = 0; s2 < T.S; ++s2) {
-            const int32_t id = s2 == 0 ? (int32_t)(tt->first + r) : tt->sid[(s2 - 1) * n + r];
-            tt->lidx[s2 * n + r] =
-                (uint16_t)(std::lower_bound(ids.begin(), ids.end(), id) - ids.begin());
-          }
-        lists[tile] = ids;
-      }
-    });
-    tt->tile_off.assign(nt + 1, 0);
-    tt->max_tile_len = 0;
-    for (int64_t k = 0; k < nt; ++k) {
-      tt->tile_off[k + 1] = tt->tile_off[k] + (int32_t)lists[k].size();
-      tt->max_tile_len = std::max<int32_t>(tt->max_tile_len, (int32_t)lists[k].size());
-    }
-    tt->tile_ids.resize(tt->tile_off[nt]);
-    for (int64_t k = 0; k < nt; ++k)
-      std::copy(lists[k].begin(), lists[k].end(), tt->tile_ids.begin() + tt->tile_off[k]);
-  }
-
   // face tables: the canonical normal and length are the left cell's
   t.fnb.assign(4 * N, -1);
   t.fgeo.assign(12 * N, 0.0);

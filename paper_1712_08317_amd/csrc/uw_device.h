@@ -1,7 +1,9 @@
 // Device-side table views and kernel launchers of the uweno library (internal).
 //
-// Work is organised in tiles: runs of up to kTileCells consecutive cells of
-// one cell type and one mesh instance (a single mesh is a batch of one).
+// Work is organised in tiles: runs of up to `tile` (256 or 512) consecutive
+// cells of one cell type and one mesh instance (a single mesh is a batch of
+// one); a reconstruction or flux block of `tile` threads works on one tile
+// at a time.
 // Quadrilateral tiles come first, then triangle tiles; within each type the
 // tiles are ordered by instance.
 #pragma once
@@ -12,12 +14,10 @@
 
 namespace uw {
 
-constexpr int kTileCells = 256;   // cells per tile = threads per block
-
 struct Tile {
   int32_t first;   // first cell (state index) of the tile
   int32_t row0;    // its row in the tables of its cell type
-  int32_t count;   // cells in the tile (<= kTileCells)
+  int32_t count;   // cells in the tile (<= the tile size)
   int32_t inst;    // mesh instance
 };
 
@@ -50,6 +50,7 @@ template <typename T>
 struct MeshDev {
   int64_t N = 0;                    // cells of all instances
   int32_t n_inst = 1;
+  int32_t tile = 256;               // cells per tile
   int32_t n_tq = 0, n_tt = 0;       // quadrilateral and triangle tiles
   const Tile* tiles = nullptr;      // [n_tq + n_tt]
   const int32_t* tile_off = nullptr;   // [n_tq + n_tt + 1] LDS staging list offsets
@@ -86,6 +87,10 @@ struct SchemeDev {
 struct Schedule {
   int recon_q = 0, recon_t = 0, flux = 0;
 };
+
+// Dynamic LDS bytes of a reconstruction block.
+template <typename T>
+size_t recon_lds(int maxlen, int nvar, int tile);
 
 // Face states at the Gauss points: FS[(i*8 + g)*V + v].
 template <typename T>

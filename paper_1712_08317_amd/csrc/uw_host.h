@@ -28,7 +28,8 @@ extern const TypeConst kTri;
 inline const TypeConst& type_const(int nf) { return nf == 4 ? kQuad : kTri; }
 
 constexpr int kMaxS = 13, kMaxM = 12, kMaxG = 8;
-constexpr int kTile = 256;   // cells per reconstruction block
+constexpr int kTile = 256;   // default cells per tile (= threads per stage block)
+inline bool tile_size_ok(int t) { return t == 256 || t == 512; }
 
 // face kind of the first moving front (kinds 3 .. kFrontKind - 1 are
 // prescribed states)
@@ -88,12 +89,6 @@ struct SchemeParams {
 struct TypeTables {
   int64_t Nt = 0, first = 0;
   std::vector<int32_t> sid;     // [S-1][Nt] cell read by slot s = 1..S-1 (after substitution)
-  // LDS staging: tiles of kTile consecutive cells; the sorted distinct cells
-  // read by a tile's stencils, and each slot's position in that list
-  std::vector<int32_t> tile_off;   // [n_tiles + 1]
-  std::vector<int32_t> tile_ids;   // [tile_off[n_tiles]]
-  std::vector<uint16_t> lidx;      // [S][Nt] (slot 0 = the cell itself)
-  int32_t max_tile_len = 0;
   std::vector<double> Y;        // [M*4][Nt] candidate operators (Y00, Y01, Y10, Y11)
   std::vector<double> off;      // [2n*2][Nt] (p^1, p^2) at each Gauss point
   std::vector<double> gam;      // [2n*M][Nt] optimised linear weights / (2 sigma+)
@@ -112,6 +107,15 @@ struct HostTables {
   double max_abs_gamma_raw = 0, max_abs_gamma_opt = 0, resid_opt = 0, sum_dev = 0;
   int64_t n_absent = 0, n_rank_def = 0;
 };
+
+// LDS staging for tiles of `tile` consecutive rows [row0, row0 + n) of one
+// cell type (cells first .. first + n - 1): for every tile, the sorted
+// distinct cells its stencils read (lists), and for every slot of every row
+// its position in that list (lidx [S][stride]).  sid: [S-1][stride] the cell
+// each slot s >= 1 reads.
+void build_tile_lists(const int32_t* sid, int64_t stride, int64_t row0, int64_t n, int64_t first,
+                      int S, int tile, int threads, uint16_t* lidx,
+                      std::vector<std::vector<int32_t>>& lists);
 
 // Host precompute (threads).
 void precompute_tables(const HostMesh& m, const SchemeParams& sp, HostTables& t, int threads);

@@ -44,5 +44,5 @@ def test_host_only_meshes_leave_the_check_to_the_library(uw):
     M.precompute()
     W = torch.zeros(M.n_cells, dtype=torch.float32)      # wrong in every way
     with pytest.raises(uw.UwError) as e:
-        M.residual(uw.make_physics(uw.UW_ADVECTION), W, W, stream=0)
+        M.residual(uw.make_physics(uw.UW_ADVECTION), W, W.clone(), stream=0)
     assert e.value.status == uw.UW_ESTATE

@@ -33,14 +33,17 @@ def batch_setup():
     return uw, torch, meshes, Ms, states
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_batch_matches_single_meshes_bitwise(batch_setup, prec):
+@pytest.mark.parametrize("prec,tile", [("fp64", 256), ("fp32", 256), ("fp32", 512)])
+def test_batch_matches_single_meshes_bitwise(batch_setup, prec, tile):
     """Each instance of the batch takes exactly the steps the single-mesh
-    path takes, including its own CFL time step."""
+    path takes with the same tile size, including its own CFL time step."""
     uw, torch, meshes, Ms, states = batch_setup
     pr = uw.UW_FP64 if prec == "fp64" else uw.UW_FP32
     ph = uw.make_physics(uw.UW_EULER, precision=pr)
+    for M in Ms:
+        M.tile_size(tile)
     B = uw.Batch(Ms, ph)
+    assert B.tile_size(tile) == tile
     assert B.offsets[-1] == sum(m.n_cells for m in meshes)
     Wb = torch.from_numpy(B.to_internal(states)).to("cuda:0")
     tb = torch.zeros(len(Ms), dtype=torch.float64, device="cuda:0")
@@ -57,6 +60,8 @@ def test_batch_matches_single_meshes_bitwise(batch_setup, prec):
         assert tb[k].item() == t.item()
     # instances of different resolution took different time steps
     assert len(set(np.round(tb.cpu().numpy(), 15))) > 2
+    for M in Ms:
+        M.tile_size(256)
 
 
 def test_batch_instance_matches_oracle(batch_setup):

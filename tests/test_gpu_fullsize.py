@@ -156,7 +156,7 @@ def test_batch_256_instances():
         samples = np.unique(np.concatenate([rng.choice(n, 4, replace=False), [0, n - 1]]))
         refs[int(k)] = (samples, op.rk3_at(meshes[k], states[k], samples,
                                            osc.Physics("euler"), dt))
-    out = {}
+    out, long = {}, {}
     for prec in ("fp64", "fp32"):
         ph = physics_for(uw, "euler", prec)
         B = uw.Batch(Ms, ph)
@@ -166,7 +166,17 @@ def test_batch_256_instances():
         B.rk3_step(Wb, tb, dt_fixed=dt, n_steps=1)
         B.check()
         out[prec] = B.to_original(Wb.cpu().numpy())
-        del Wb
+        # the workload as specified: 100 RK3 steps of every instance, each
+        # with its own CFL time step, as captured graph replays
+        Wb = torch.from_numpy(B.to_internal(states)).to("cuda:0")
+        tb.zero_()
+        for _ in range(10):
+            B.rk3_step(Wb, tb, cfl=0.5, n_steps=10)
+        B.check()
+        long[prec] = (B.to_original(Wb.cpu().numpy()), tb.cpu().numpy())
+        print(f"{prec}: tile {B.tile_size()}, schedule {B.schedule()}, 100 steps to "
+              f"t in [{tb.min().item():.4f}, {tb.max().item():.4f}]", flush=True)
+        del Wb, B
     got = {p: np.concatenate([out[p][k][:, refs[k][0]] for k in refs], 1) for p in out}
     ref = np.concatenate([refs[k][1] for k in refs], 1)
     e64, e32 = parity_err(got["fp64"], ref, 1e-12), parity_err(got["fp32"], ref, 1e-5)
@@ -174,6 +184,12 @@ def test_batch_256_instances():
           f"fp32 {e32:.3e}", flush=True)
     assert e64 <= 1e-12
     assert e32 <= 1e-5
+    # FP32 against FP64 on the same device after 100 steps, every instance
+    worst = max(parity_err(a, b, 1e-5) for a, b in zip(long["fp32"][0], long["fp64"][0]))
+    print(f"100 steps, fp32 vs fp64, worst instance: {worst:.3e}", flush=True)
+    assert worst <= 1e-5
+    # the CFL steps depend on the state: FP32 and FP64 times agree closely
+    assert np.allclose(long["fp32"][1], long["fp64"][1], rtol=1e-6, atol=0)
 
 
 def test_rotated_sod_fp32_long_run():

@@ -306,3 +306,36 @@ def test_graphs_follow_physics_and_moved_work_buffers():
     ga, ge = run(True, seq)
     ea, ee = run(False, seq)
     assert torch.equal(ga, ea) and torch.equal(ge, ee)
+
+
+@pytest.mark.parametrize("name", ["mixed", "quad", "tri", "sod"])
+def test_tile_sizes_fp32_match_oracle(name):
+    """The stage kernels with 512-cell tiles (FP32, WENO on the conserved
+    variables): a residual and three RK3 steps against the oracle, and the
+    kernels that exist for 256-cell tiles only refuse the tile size."""
+    import torch
+    uw, mesh, M, T = _setup(name)
+    W = _state(name, mesh, 16)
+    try:
+        assert M.tile_size(512) == 512
+        ref = osc.residual_vectorized(T, W, osc.Physics("euler"))
+        got = gpu_residual(uw, M, W, "euler", "fp32")
+        assert parity_err(got, ref, 1e-5) <= 1e-5
+        with pytest.raises(uw.UwError) as e:
+            gpu_residual(uw, M, W, "euler", "fp64")
+        assert e.value.status == uw.UW_EINVAL
+        ph = osc.Physics("euler")
+        dt = 0.5 * osc.cfl_dt(T, W, ph, 0.5)
+        ref = W.copy()
+        for _ in range(3):
+            ref = osc.rk3_step(T, ref, ph, dt)
+        Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        for _ in range(3):
+            M.rk3_step(physics_for(uw, "euler", "fp32"), Wd, t, dt_fixed=dt)
+        M.check()
+        err = parity_err(M.to_original(Wd.cpu().numpy()), ref, 1e-5)
+        print(name, "tile 512 fp32 rk3 rel err", err)
+        assert err <= 1e-5
+    finally:
+        M.tile_size(256)

@@ -111,8 +111,9 @@ def test_call_order_and_arguments(uw):
     M = uw.Mesh.from_workload(mesh, device=-1)
     ph = uw.make_physics()
     W = np.zeros((4, M.n_cells))
+    L = np.zeros_like(W)
     with pytest.raises(uw.UwError) as e:
-        M.residual(ph, W, W, stream=0)
+        M.residual(ph, W, L, stream=0)
     assert e.value.status == uw.UW_ESTATE
     with pytest.raises(uw.UwError) as e:
         M.table(0)
@@ -125,17 +126,17 @@ def test_call_order_and_arguments(uw):
     assert e.value.status == uw.UW_EINVAL
     M.precompute()
     with pytest.raises(uw.UwError) as e:        # host-only mesh
-        M.residual(ph, W, W, stream=0)
+        M.residual(ph, W, L, stream=0)
     assert e.value.status == uw.UW_ESTATE
     with pytest.raises(uw.UwError) as e:        # host-only mesh, no-allocation variant
-        M.residual_noalloc(ph, W, W, stream=0)
+        M.residual_noalloc(ph, W, L, stream=0)
     assert e.value.status == uw.UW_ESTATE
     bad = uw.make_physics(equation=7)
     with pytest.raises(uw.UwError) as e:
-        M.residual(bad, W, W, stream=0)
+        M.residual(bad, W, L, stream=0)
     assert e.value.status == uw.UW_EINVAL
     with pytest.raises(uw.UwError) as e:
-        M.residual_noalloc(bad, W, W, stream=0)
+        M.residual_noalloc(bad, W, L, stream=0)
     assert e.value.status == uw.UW_EINVAL
     st = uw.LIB.uw_mesh_upload(None, -1, None)
     assert st == uw.UW_EINVAL

@@ -57,8 +57,8 @@ def test_noalloc_residual_equals_residual(prec):
 
 
 def test_noalloc_residual_size_limit():
-    """270,400 cells: FP64 Euler face states need 138 MB > 64 MiB (refused
-    before any launch, UW_EINVAL); FP32 needs 34.6 MB (runs, equal to
+    """270,400 cells: FP64 Euler face states need 69.2 MB > 64 MiB, refused
+    before any launch (UW_EINVAL); FP32 needs 34.6 MB (runs, equal to
     uw_residual)."""
     import torch
     import paper_1712_08317_amd as uw
