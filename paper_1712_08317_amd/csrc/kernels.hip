@@ -521,14 +521,18 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double
 // states, written out in one coalesced block per tile.
 // KIND: 0 WENO on the conserved variables, 1 the linear scheme, 2 WENO on
 // the characteristic variables (Euler).
-template <typename T, int NF, int V, int KIND>
 // Occupancy measured on gfx950 (FP32): the WENO kernels run fastest with 2
 // waves per SIMD forced (256 VGPRs each; the quadrilateral ones then spill a
 // few values: the characteristic kernel runs 39% faster than at 1 wave, the
 // conserved one, which reads its weights one point ahead, 4% faster than
 // without that prefetch, when it fitted 2 waves unspilled).  The FP32 linear
-// kernels and every FP64 kernel keep the whole register file.
-__global__ __launch_bounds__(kTileCells, sizeof(T) == 4 && (NF == 3 || KIND != 1) ? 2 : 1) void k_recon(
+// kernels and every FP64 kernel keep the whole register file.  Blocks of
+// TILE threads: 2 waves per SIMD are 512 / TILE blocks per compute unit.
+template <typename T, int NF, int KIND, int TILE>
+constexpr int kReconBlocksPerCu = (sizeof(T) == 4 && (NF == 3 || KIND != 1) ? 2 : 1) * 256 / TILE;
+
+template <typename T, int NF, int V, int KIND, int TILE>
+__global__ __launch_bounds__(TILE, (kReconBlocksPerCu<T, NF, KIND, TILE>)) void k_recon(
     const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
   extern __shared__ double lds[];
   const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
@@ -652,8 +656,8 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
 // were fetched again for later faces).  The FP64 kernel reads FS directly:
 // its 256-byte records would fill 68 KB of LDS per block, and at two blocks
 // per CU it ran 25% slower.
-template <typename T, int V, int MODE, bool FRONTS>
-__global__ __launch_bounds__(kTileCells) void k_flux(MeshDev<T> m, PhysDev p,
+template <typename T, int V, int MODE, bool FRONTS, int TILE>
+__global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
                                                      const T* __restrict__ FS, const double* W_in,
                                                      const double* Wn, double* W_out,
                                                      const double* __restrict__ dtp, int* flag) {
@@ -761,18 +765,20 @@ __device__ inline double wave_min(double x) {
 }
 
 // Local time-step bound of every cell of one tile, reduced to the tile's
-// minimum (wavefront then block).
+// minimum (wavefront then block); one 256-thread block per tile of any size.
+constexpr int kCflBlock = 256;
 template <typename T, int V>
-__global__ __launch_bounds__(kTileCells) void k_cfl(MeshDev<T> m, PhysDev p,
-                                                    const double* __restrict__ W,
-                                                    double* __restrict__ partial) {
-  __shared__ double red[kTileCells / 64];
+__global__ __launch_bounds__(kCflBlock) void k_cfl(MeshDev<T> m, PhysDev p,
+                                                   const double* __restrict__ W,
+                                                   double* __restrict__ partial) {
+  __shared__ double red[kCflBlock / 64];
   const int tile = blockIdx.x;
   const Tile tl = m.tiles[tile];
   const int64_t N = m.N;
+  const int nf = tile < m.n_tq ? 4 : 3;
   double x = INFINITY;
-  if ((int)threadIdx.x < tl.count) {
-    const int64_t i = tl.first + threadIdx.x;
+  for (int j = threadIdx.x; j < tl.count; j += kCflBlock) {
+    const int64_t i = tl.first + j;
     double u, v, c;
     if (V == 4) {
       const double rho = W[i], mu = W[N + i], mv = W[2 * N + i], E = W[3 * N + i];
@@ -785,14 +791,13 @@ __global__ __launch_bounds__(kTileCells) void k_cfl(MeshDev<T> m, PhysDev p,
       v = p.ay;
       c = 0.0;
     }
-    const int nf = tile < m.n_tq ? 4 : 3;
     double s = 0.0;
     for (int k = 0; k < nf; ++k) {
       const double nx = m.fnrm[(k * 2 + 0) * N + i], ny = m.fnrm[(k * 2 + 1) * N + i];
       const double coef = m.fcoef[k * N + i];
       s += coef * (fabs(u * nx + v * ny) + c);
     }
-    x = 1.0 / s;
+    x = fmin(x, 1.0 / s);
   }
   x = wave_min(x);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -800,7 +805,7 @@ __global__ __launch_bounds__(kTileCells) void k_cfl(MeshDev<T> m, PhysDev p,
   __syncthreads();
   if (threadIdx.x == 0) {
     double b = red[0];
-    for (int w = 1; w < kTileCells / 64; ++w) b = fmin(b, red[w]);
+    for (int w = 1; w < kCflBlock / 64; ++w) b = fmin(b, red[w]);
     partial[tile] = b;
   }
 }
@@ -861,6 +866,14 @@ size_t lds_limit() {
 }
 
 template <typename T>
+size_t recon_lds(int maxlen, int nvar, int tile) {
+  return (size_t)((maxlen * nvar + 1) & ~1) * sizeof(double) +
+         (size_t)tile * (8 * nvar * sizeof(T) + 16);
+}
+
+// 512-cell tiles exist for the FP32 WENO kernels on the conserved variables;
+// everything else runs 256-cell tiles.
+template <typename T>
 hipError_t launch_recon(const MeshDev<T>& m0, const SchemeDev& s, const PhysDev& p,
                         const Schedule& sch, int nvar, const double* W, T* FS,
                         const StageTime& tm, hipStream_t st) {
@@ -868,25 +881,37 @@ hipError_t launch_recon(const MeshDev<T>& m0, const SchemeDev& s, const PhysDev&
   m.tm = tm;
   const int kind = s.mode == 1 ? 1 : (s.vars == 1 && nvar == 4 ? 2 : 0);
   const T eps = (T)s.eps, th = (T)s.theta, gam = (T)p.gamma;
+  if (m.tile != 256 && !(m.tile == 512 && sizeof(T) == 4 && kind == 0))
+    return hipErrorInvalidValue;
   auto one = [&](int ntiles, int maxlen, int want, auto nf_tag) -> hipError_t {
     constexpr int NF = decltype(nf_tag)::value;
     if (ntiles <= 0) return hipSuccess;
     const unsigned grid = (unsigned)(want > 0 && want < ntiles ? want : ntiles);
-    const size_t shm = (size_t)((maxlen * nvar + 1) & ~1) * sizeof(double) +
-                       (size_t)kTileCells * (8 * nvar * sizeof(T) + 16);
+    const size_t shm = recon_lds<T>(maxlen, nvar, m.tile);
     if (shm > lds_limit()) return hipErrorInvalidConfiguration;
+    auto go = [&](auto v_tag, auto kind_tag, auto tile_tag) {
+      constexpr int V = decltype(v_tag)::value, K = decltype(kind_tag)::value;
+      constexpr int TL = decltype(tile_tag)::value;
+      k_recon<T, NF, V, K, TL><<<grid, TL, shm, st>>>(W, m, FS, eps, th, gam);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I4 = std::integral_constant<int, 4>;
+    using T256 = std::integral_constant<int, 256>;
     if (kind == 1) {
-      if (nvar == 4)
-        k_recon<T, NF, 4, 1><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
-      else
-        k_recon<T, NF, 1, 1><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
+      if (nvar == 4) go(I4{}, I1{}, T256{});
+      else go(I1{}, I1{}, T256{});
     } else if (kind == 2) {
-      k_recon<T, NF, 4, 2><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
+      go(I4{}, std::integral_constant<int, 2>{}, T256{});
     } else {
-      if (nvar == 4)
-        k_recon<T, NF, 4, 0><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
-      else
-        k_recon<T, NF, 1, 0><<<grid, kTileCells, shm, st>>>(W, m, FS, eps, th, gam);
+      auto by_tile = [&](auto v_tag) {
+        if constexpr (sizeof(T) == 4) {
+          if (m.tile == 512) return go(v_tag, I0{}, std::integral_constant<int, 512>{});
+        }
+        go(v_tag, I0{}, T256{});
+      };
+      if (nvar == 4) by_tile(I4{});
+      else by_tile(I1{});
     }
     return hipGetLastError();
   };
@@ -904,16 +929,24 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
   const int ntiles = m.n_tq + m.n_tt;
   if (ntiles <= 0) return hipSuccess;
   const unsigned grid = (unsigned)(sch.flux > 0 && sch.flux < ntiles ? sch.flux : ntiles);
+  if (m.tile != 256 && !(m.tile == 512 && sizeof(T) == 4)) return hipErrorInvalidValue;
   // one padded record row per cell of a tile (FP32)
-  const size_t shm = sizeof(T) == 4 ? (size_t)kTileCells * (8 * nvar * sizeof(T) + 16) : 0;
+  const size_t shm = sizeof(T) == 4 ? (size_t)m.tile * (8 * nvar * sizeof(T) + 16) : 0;
   if (shm > lds_limit()) return hipErrorInvalidConfiguration;
   // meshes without front faces get the instantiation without the front case
-  auto go = [&](auto v_tag, auto mode_tag) {
+  auto go2 = [&](auto v_tag, auto mode_tag, auto tile_tag) {
     constexpr int V = decltype(v_tag)::value, MD = decltype(mode_tag)::value;
+    constexpr int TL = decltype(tile_tag)::value;
     if (m.fronts)
-      k_flux<T, V, MD, true><<<grid, kTileCells, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+      k_flux<T, V, MD, true, TL><<<grid, TL, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
     else
-      k_flux<T, V, MD, false><<<grid, kTileCells, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+      k_flux<T, V, MD, false, TL><<<grid, TL, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+  };
+  auto go = [&](auto v_tag, auto mode_tag) {
+    if constexpr (sizeof(T) == 4) {
+      if (m.tile == 512) return go2(v_tag, mode_tag, std::integral_constant<int, 512>{});
+    }
+    go2(v_tag, mode_tag, std::integral_constant<int, 256>{});
   };
   auto by_mode = [&](auto v_tag) {
     switch (mode) {
@@ -937,9 +970,9 @@ hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const dou
   const int ntiles = m.n_tq + m.n_tt;
   if (dt_fixed <= 0.0 && ntiles > 0) {
     if (nvar == 4)
-      k_cfl<T, 4><<<(unsigned)ntiles, kTileCells, 0, st>>>(m, p, W, partial);
+      k_cfl<T, 4><<<(unsigned)ntiles, kCflBlock, 0, st>>>(m, p, W, partial);
     else
-      k_cfl<T, 1><<<(unsigned)ntiles, kTileCells, 0, st>>>(m, p, W, partial);
+      k_cfl<T, 1><<<(unsigned)ntiles, kCflBlock, 0, st>>>(m, p, W, partial);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -952,6 +985,8 @@ hipError_t launch_advance(int n_inst, double* t, const double* dt, hipStream_t s
   return hipGetLastError();
 }
 
+template size_t recon_lds<double>(int, int, int);
+template size_t recon_lds<float>(int, int, int);
 template hipError_t launch_recon<double>(const MeshDev<double>&, const SchemeDev&, const PhysDev&,
                                          const Schedule&, int, const double*, double*,
                                          const StageTime&, hipStream_t);
