@@ -242,9 +242,21 @@ uw_status uw_residual_at(uw_mesh* mesh, const uw_physics* physics, const double*
  * the step's launches into a hipGraph and later calls replay it (the null
  * stream is served by a library stream ordered with it); while per-kernel
  * timing is on (uw_profile) the launches are issued one by one instead.
- * uw_precompute_geometry, uw_autotune and uw_schedule drop the graphs. */
+ * At most 8 graphs are kept per mesh or batch: a new argument set beyond
+ * that first waits for the device, then drops the least recently used one.
+ * uw_precompute_geometry, uw_autotune, uw_schedule and uw_tile_size drop
+ * the graphs (after the device has finished). */
 uw_status uw_rk3_step(uw_mesh* mesh, const uw_physics* physics, double* W, double cfl,
                       double dt_fixed, double t_end, double* t_dev, void* stream);
+
+/* n_steps (>= 0) steps of uw_rk3_step in one call, captured together (the
+ * graph key adds n_steps).  Inside the run, the last stage of each step
+ * also forms the next step's CFL bound from the state it writes (the same
+ * value a separate pass over W gives), so a step after the first reads W
+ * once less.  Errors: as uw_rk3_step. */
+uw_status uw_rk3_steps(uw_mesh* mesh, const uw_physics* physics, double* W, double cfl,
+                       double dt_fixed, double t_end, int32_t n_steps, double* t_dev,
+                       void* stream);
 
 /* The CFL time step alone: dt_dev (device double) = cfl * min_i
  * 2|Omega_i| / sum_p |l_p| (|u_i.n_p| + c_i), from cell averages W. */

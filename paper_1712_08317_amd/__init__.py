@@ -76,7 +76,7 @@ class DiagC(ctypes.Structure):
 
 EXPORTS = ["uw_last_error", "uw_mesh_upload", "uw_mesh_info", "uw_mesh_export",
            "uw_precompute_geometry", "uw_mesh_table", "uw_residual", "uw_residual_at",
-           "uw_residual_noalloc", "uw_rk3_step",
+           "uw_residual_noalloc", "uw_rk3_step", "uw_rk3_steps",
            "uw_cfl_dt",
            "uw_batch_create", "uw_batch_offsets", "uw_batch_rk3_step", "uw_autotune", "uw_check",
            "uw_profile", "uw_schedule", "uw_tile_size", "uw_mesh_destroy", "uw_batch_destroy"]
@@ -101,6 +101,7 @@ def _load():
         "uw_residual_at": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, dbl, vp]),
         "uw_residual_noalloc": (i32, [vp, ctypes.POINTER(PhysicsC), vp, vp, vp]),
         "uw_rk3_step": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, dbl, dbl, vp, vp]),
+        "uw_rk3_steps": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, dbl, dbl, i32, vp, vp]),
         "uw_cfl_dt": (i32, [vp, ctypes.POINTER(PhysicsC), vp, dbl, vp, vp]),
         "uw_batch_create": (i32, [vp, i32, ctypes.POINTER(PhysicsC), ctypes.POINTER(vp)]),
         "uw_batch_offsets": (i32, [vp, vp]),
@@ -293,6 +294,13 @@ class Mesh:
         self._check_state(physics, W=W, t_dev=t_dev)
         _check(LIB.uw_rk3_step(self.handle, ctypes.byref(physics), _ptr(W), cfl, dt_fixed, t_end,
                                _ptr(t_dev), _stream(stream)))
+
+    def rk3_steps(self, physics: PhysicsC, W, t_dev, n_steps, cfl=0.5, dt_fixed=0.0,
+                  t_end=float("inf"), stream=None):
+        """n_steps SSP-RK3 steps in one call (one captured graph)."""
+        self._check_state(physics, W=W, t_dev=t_dev)
+        _check(LIB.uw_rk3_steps(self.handle, ctypes.byref(physics), _ptr(W), cfl, dt_fixed,
+                                t_end, int(n_steps), _ptr(t_dev), _stream(stream)))
 
     def cfl_dt(self, physics: PhysicsC, W, cfl, dt_dev, stream=None):
         self._check_state(physics, W=W, dt_dev=dt_dev)

@@ -342,11 +342,15 @@ struct Engine {
   bool profiling = false;
   std::vector<hipEvent_t> ev_pool;
   std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
-  // captured multi-step graphs, keyed by their arguments
+  // captured multi-step graphs, keyed by their arguments, with the serial
+  // number of their last use; at most kMaxGraphs are kept (least recently
+  // used evicted), so callers that vary the arguments do not accumulate them
+  static constexpr size_t kMaxGraphs = 8;
   std::map<std::tuple<const void*, const void*, int, double, double, double, int, double, double,
                       double>,
-           hipGraphExec_t>
+           std::pair<hipGraphExec_t, uint64_t>>
       graphs;
+  uint64_t graph_uses = 0;
   // graphs cannot be captured on the null stream: calls made on it capture
   // and replay on this blocking stream, which orders itself with the null one
   hipStream_t own_stream = nullptr;
@@ -356,7 +360,12 @@ struct Engine {
     clear_graphs();
   }
   void clear_graphs() {
-    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second);
+    // a graph may still be running: let the device finish before destroying
+    if (!graphs.empty() && device >= 0) {
+      (void)hipSetDevice(device);
+      (void)hipDeviceSynchronize();
+    }
+    for (auto& g : graphs) (void)hipGraphExecDestroy(g.second.first);
     graphs.clear();
   }
   ~Engine() {
@@ -531,7 +540,7 @@ hipError_t ev_begin(Engine& E, hipStream_t st, hipEvent_t* a, hipEvent_t* b) {
 template <class T>
 uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, const double* Wn,
                 double* W_out, const uw::StageTime& tm, hipStream_t st, bool timed,
-                T* FS = nullptr) {
+                T* FS = nullptr, double* partial = nullptr) {
   const int nvar = nvar_of(p);
   DevTables<T>& d = tables_of<T>(E);
   if (!FS) FS = E.FS.template as<T>();
@@ -551,7 +560,7 @@ uw_status stage(Engine& E, const uw_physics* p, int mode, const double* W_in, co
     UW_HIP(ev_begin(E, st, &a, &b));
   }
   e = uw::launch_flux<T>(d.view, phys_dev(p), E.sched, nvar, mode, FS, W_in, Wn, W_out,
-                         E.dt.as<double>(), E.flag.as<int>(), tm, st);
+                         E.dt.as<double>(), E.flag.as<int>(), tm, st, partial);
   if (e != hipSuccess) return hip_fail(e, "flux launch");
   if (prof) {
     UW_HIP(hipEventRecord(b, st));
@@ -566,20 +575,27 @@ uw_status prepare(Engine& E, const uw_physics* p) {
   return ensure_work(E, nvar_of(p), sizeof(T));
 }
 
-// One SSP-RK3 step of every instance (time step on the device).
+// One SSP-RK3 step of every instance (time step on the device).  Inside a
+// run of steps the last stage's flux launch forms the next step's per-tile
+// time-step bounds (make_partial), and the next step then only reduces them
+// (have_partial): the same bounds, from the same states and formula, as a
+// separate pass over W.
 template <class T>
 uw_status rk3(Engine& E, const uw_physics* p, double* W, double cfl, double dt_fixed,
-              double t_end, double* t_dev, hipStream_t st, bool timed) {
+              double t_end, double* t_dev, hipStream_t st, bool timed,
+              bool have_partial = false, bool make_partial = false) {
   DevTables<T>& d = tables_of<T>(E);
   hipError_t e = uw::launch_cfl<T>(d.view, phys_dev(p), nvar_of(p), W, cfl, dt_fixed, t_end,
-                                   t_dev, E.partial.as<double>(), E.dt.as<double>(), st);
+                                   t_dev, E.partial.as<double>(), E.dt.as<double>(), st,
+                                   have_partial && dt_fixed <= 0.0);
   if (e != hipSuccess) return hip_fail(e, "time-step launch");
   double* W1 = E.Wtmp.as<double>();
   // the stages see the boundary data at t, t + dt and t + dt/2
   const double* dtp = E.dt.as<double>();
   UW_TRY(stage<T>(E, p, 1, W, W, W1, uw::StageTime{t_dev, dtp, 0.0, 0.0}, st, timed));
   UW_TRY(stage<T>(E, p, 2, W1, W, W1, uw::StageTime{t_dev, dtp, 1.0, 0.0}, st, timed));
-  UW_TRY(stage<T>(E, p, 3, W1, W, W, uw::StageTime{t_dev, dtp, 0.5, 0.0}, st, timed));
+  UW_TRY(stage<T>(E, p, 3, W1, W, W, uw::StageTime{t_dev, dtp, 0.5, 0.0}, st, timed, nullptr,
+                  make_partial && dt_fixed <= 0.0 ? E.partial.as<double>() : nullptr));
   e = uw::launch_advance(E.staged.n_inst, t_dev, E.dt.as<double>(), st);
   if (e != hipSuccess) return hip_fail(e, "time advance launch");
   return UW_OK;
@@ -591,7 +607,7 @@ uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, doubl
   UW_TRY(prepare<T>(E, p));
   if (!graph || n_steps <= 0) {
     for (int k = 0; k < n_steps; ++k)
-      UW_TRY(rk3<T>(E, p, W, cfl, dt_fixed, t_end, t_dev, st, true));
+      UW_TRY(rk3<T>(E, p, W, cfl, dt_fixed, t_end, t_dev, st, true, k > 0, k + 1 < n_steps));
     return UW_OK;
   }
   if (!st) {
@@ -602,10 +618,20 @@ uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, doubl
                              p->precision * 16 + p->equation, p->gamma, p->ax, p->ay);
   auto it = E.graphs.find(key);
   if (it == E.graphs.end()) {
+    if (E.graphs.size() >= Engine::kMaxGraphs) {
+      // evict the least recently used graph, after the device has finished
+      // anything it may still be running
+      auto lru = E.graphs.begin();
+      for (auto g = E.graphs.begin(); g != E.graphs.end(); ++g)
+        if (g->second.second < lru->second.second) lru = g;
+      UW_HIP(hipDeviceSynchronize());
+      (void)hipGraphExecDestroy(lru->second.first);
+      E.graphs.erase(lru);
+    }
     UW_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
     uw_status s = UW_OK;
     for (int k = 0; k < n_steps && s == UW_OK; ++k)
-      s = rk3<T>(E, p, W, cfl, dt_fixed, t_end, t_dev, st, false);
+      s = rk3<T>(E, p, W, cfl, dt_fixed, t_end, t_dev, st, false, k > 0, k + 1 < n_steps);
     hipGraph_t g = nullptr;
     hipError_t e = hipStreamEndCapture(st, &g);
     if (s != UW_OK) {
@@ -617,9 +643,10 @@ uw_status rk3_steps(Engine& E, const uw_physics* p, double* W, double cfl, doubl
     e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return hip_fail(e, "hipGraphInstantiate");
-    it = E.graphs.emplace(key, ex).first;
+    it = E.graphs.emplace(key, std::make_pair(ex, uint64_t{0})).first;
   }
-  UW_HIP(hipGraphLaunch(it->second, st));
+  it->second.second = ++E.graph_uses;
+  UW_HIP(hipGraphLaunch(it->second.first, st));
   return UW_OK;
 }
 
@@ -919,20 +946,27 @@ uw_status uw_residual_noalloc(uw_mesh* m, const uw_physics* p, const double* W, 
   return residual_noalloc<float>(m->eng, p, W, L, st);
 }
 
-uw_status uw_rk3_step(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,
-                      double t_end, double* t_dev, void* stream) {
+uw_status uw_rk3_steps(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,
+                       double t_end, int32_t n_steps, double* t_dev, void* stream) {
   g_err.clear();
   if (!m || !W || !t_dev) return fail(UW_EINVAL, "mesh, W and t_dev must not be NULL");
+  if (n_steps < 0) return fail(UW_EINVAL, "n_steps must be >= 0");
   UW_TRY(check_physics(p));
   if (!(dt_fixed > 0.0) && !(cfl > 0.0)) return fail(UW_EINVAL, "need cfl > 0 or dt_fixed > 0");
   UW_TRY(mesh_ready(m));
   hipStream_t st = (hipStream_t)stream;
-  // replay a captured graph of the step (one launch instead of about a dozen)
-  // unless per-kernel timing is on, which records events between launches
+  // replay a captured graph of the steps (one launch instead of about a
+  // dozen per step) unless per-kernel timing is on, which records events
+  // between launches
   const bool graph = !m->eng.profiling;
   if (p->precision == UW_FP64)
-    return rk3_steps<double>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, graph);
-  return rk3_steps<float>(m->eng, p, W, cfl, dt_fixed, t_end, 1, t_dev, st, graph);
+    return rk3_steps<double>(m->eng, p, W, cfl, dt_fixed, t_end, n_steps, t_dev, st, graph);
+  return rk3_steps<float>(m->eng, p, W, cfl, dt_fixed, t_end, n_steps, t_dev, st, graph);
+}
+
+uw_status uw_rk3_step(uw_mesh* m, const uw_physics* p, double* W, double cfl, double dt_fixed,
+                      double t_end, double* t_dev, void* stream) {
+  return uw_rk3_steps(m, p, W, cfl, dt_fixed, t_end, 1, t_dev, stream);
 }
 
 uw_status uw_cfl_dt(uw_mesh* m, const uw_physics* p, const double* W, double cfl, double* dt_dev,

@@ -643,6 +643,42 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
   }
 }
 
+__device__ inline double wave_min(double x) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
+  return x;
+}
+
+// Local time-step bound 1 / sum_p (|l_p| / (2 |Omega|)) (|u.n_p| + c) of
+// cell i with state w, written out without contractions so that every
+// kernel that forms it (k_cfl from a state, k_flux from the state it has
+// just written) gets the same bits.
+template <typename T, int V>
+__device__ inline double cell_dt_bound(const MeshDev<T>& m, const PhysDev& p, int nf, int64_t i,
+                                       const double (&w)[V]) {
+#pragma clang fp contract(off)
+  const int64_t N = m.N;
+  double u, v, c;
+  if constexpr (V == 4) {
+    const double rho = w[0], mu = w[1], mv = w[2], E = w[3];
+    u = mu / rho;
+    v = mv / rho;
+    const double pr = (p.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
+    c = sqrt(p.gamma * pr / rho);
+  } else {
+    u = p.ax;
+    v = p.ay;
+    c = 0.0;
+  }
+  double s = 0.0;
+  for (int k = 0; k < nf; ++k) {
+    const double nx = m.fnrm[(k * 2 + 0) * N + i], ny = m.fnrm[(k * 2 + 1) * N + i];
+    const double coef = m.fcoef[k * N + i];
+    s += coef * (fabs(u * nx + v * ny) + c);
+  }
+  return 1.0 / s;
+}
+
 // FRONTS: the mesh has moving-front faces.  Measured on gfx950: the flux
 // kernel runs 8% slower on meshes without such faces when the front case is
 // compiled in, although it never executes, so it has an instantiation
@@ -656,12 +692,18 @@ __device__ inline void face_flux(const T* WL, const T* WR, T nx, T ny, const Phy
 // were fetched again for later faces).  The FP64 kernel reads FS directly:
 // its 256-byte records would fill 68 KB of LDS per block, and at two blocks
 // per CU it ran 25% slower.
+// partial (nullable): the time-step bound of the next step, each tile's
+// minimum of cell_dt_bound over the states this launch writes (the last
+// stage of a step), so that the next step needs no time-step pass of its
+// own.
 template <typename T, int V, int MODE, bool FRONTS, int TILE>
 __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
                                                      const T* __restrict__ FS, const double* W_in,
                                                      const double* Wn, double* W_out,
-                                                     const double* __restrict__ dtp, int* flag) {
+                                                     const double* __restrict__ dtp, int* flag,
+                                                     double* __restrict__ partial) {
   extern __shared__ double lds[];
+  __shared__ double red[TILE / 64];
   T* rec = reinterpret_cast<T*>(lds);
   constexpr int REC = 8 * V;              // face-state values per cell
   constexpr int PER = 16 / sizeof(T);     // values per 16-byte unit
@@ -683,6 +725,7 @@ __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
       }
     }
     __syncthreads();
+    double bound = INFINITY;
     if ((int)threadIdx.x < tl.count) {
       const int64_t i = tl.first + threadIdx.x;
       const T* own = STAGE ? rec + threadIdx.x * STRIDE : FS + i * REC;
@@ -736,6 +779,7 @@ __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
       }
       double dt = 0.0;
       if (MODE != 0) dt = dtp[tl.inst];
+      double outs[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const double Lv = -acc[v];
@@ -751,17 +795,23 @@ __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
         }
         bad |= !isfinite(out);
         W_out[v * N + i] = out;
+        outs[v] = out;
       }
       if (bad && flag) *flag = 1;
+      if (partial) bound = cell_dt_bound<T, V>(m, p, nf, i, outs);
+    }
+    if (partial) {   // uniform: every thread of the block takes this branch
+      bound = wave_min(bound);
+      if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = bound;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double b = red[0];
+        for (int w = 1; w < TILE / 64; ++w) b = fmin(b, red[w]);
+        partial[tile] = b;
+      }
     }
     __syncthreads();   // the next tile overwrites the records
   }
-}
-
-__device__ inline double wave_min(double x) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x = fmin(x, __shfl_xor(x, o, 64));
-  return x;
 }
 
 // Local time-step bound of every cell of one tile, reduced to the tile's
@@ -779,25 +829,10 @@ __global__ __launch_bounds__(kCflBlock) void k_cfl(MeshDev<T> m, PhysDev p,
   double x = INFINITY;
   for (int j = threadIdx.x; j < tl.count; j += kCflBlock) {
     const int64_t i = tl.first + j;
-    double u, v, c;
-    if (V == 4) {
-      const double rho = W[i], mu = W[N + i], mv = W[2 * N + i], E = W[3 * N + i];
-      u = mu / rho;
-      v = mv / rho;
-      const double pr = (p.gamma - 1.0) * (E - 0.5 * rho * (u * u + v * v));
-      c = sqrt(p.gamma * pr / rho);
-    } else {
-      u = p.ax;
-      v = p.ay;
-      c = 0.0;
-    }
-    double s = 0.0;
-    for (int k = 0; k < nf; ++k) {
-      const double nx = m.fnrm[(k * 2 + 0) * N + i], ny = m.fnrm[(k * 2 + 1) * N + i];
-      const double coef = m.fcoef[k * N + i];
-      s += coef * (fabs(u * nx + v * ny) + c);
-    }
-    x = fmin(x, 1.0 / s);
+    double w[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) w[v] = W[v * N + i];
+    x = fmin(x, cell_dt_bound<T, V>(m, p, nf, i, w));
   }
   x = wave_min(x);
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -923,7 +958,8 @@ hipError_t launch_recon(const MeshDev<T>& m0, const SchemeDev& s, const PhysDev&
 template <typename T>
 hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& sch, int nvar,
                        int mode, const T* FS, const double* W_in, const double* Wn, double* W_out,
-                       const double* dt, int* flag, const StageTime& tm, hipStream_t st) {
+                       const double* dt, int* flag, const StageTime& tm, hipStream_t st,
+                       double* partial) {
   MeshDev<T> m = m0;
   m.tm = tm;
   const int ntiles = m.n_tq + m.n_tt;
@@ -938,9 +974,11 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
     constexpr int V = decltype(v_tag)::value, MD = decltype(mode_tag)::value;
     constexpr int TL = decltype(tile_tag)::value;
     if (m.fronts)
-      k_flux<T, V, MD, true, TL><<<grid, TL, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+      k_flux<T, V, MD, true, TL><<<grid, TL, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag,
+                                                        partial);
     else
-      k_flux<T, V, MD, false, TL><<<grid, TL, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag);
+      k_flux<T, V, MD, false, TL><<<grid, TL, shm, st>>>(m, p, FS, W_in, Wn, W_out, dt, flag,
+                                                         partial);
   };
   auto go = [&](auto v_tag, auto mode_tag) {
     if constexpr (sizeof(T) == 4) {
@@ -966,9 +1004,9 @@ hipError_t launch_flux(const MeshDev<T>& m0, const PhysDev& p, const Schedule& s
 template <typename T>
 hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const double* W, double cfl,
                       double dt_fixed, double t_end, const double* t, double* partial,
-                      double* dt, hipStream_t st) {
+                      double* dt, hipStream_t st, bool have_partial) {
   const int ntiles = m.n_tq + m.n_tt;
-  if (dt_fixed <= 0.0 && ntiles > 0) {
+  if (dt_fixed <= 0.0 && ntiles > 0 && !have_partial) {
     if (nvar == 4)
       k_cfl<T, 4><<<(unsigned)ntiles, kCflBlock, 0, st>>>(m, p, W, partial);
     else
@@ -996,15 +1034,16 @@ template hipError_t launch_recon<float>(const MeshDev<float>&, const SchemeDev&,
 template hipError_t launch_flux<double>(const MeshDev<double>&, const PhysDev&, const Schedule&,
                                         int, int, const double*, const double*, const double*,
                                         double*, const double*, int*, const StageTime&,
-                                        hipStream_t);
+                                        hipStream_t, double*);
 template hipError_t launch_flux<float>(const MeshDev<float>&, const PhysDev&, const Schedule&, int,
                                        int, const float*, const double*, const double*, double*,
-                                       const double*, int*, const StageTime&, hipStream_t);
+                                       const double*, int*, const StageTime&, hipStream_t,
+                                       double*);
 template hipError_t launch_cfl<double>(const MeshDev<double>&, const PhysDev&, int, const double*,
                                        double, double, double, const double*, double*, double*,
-                                       hipStream_t);
+                                       hipStream_t, bool);
 template hipError_t launch_cfl<float>(const MeshDev<float>&, const PhysDev&, int, const double*,
                                       double, double, double, const double*, double*, double*,
-                                      hipStream_t);
+                                      hipStream_t, bool);
 
 }  // namespace uw

@@ -100,18 +100,22 @@ hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& 
 
 // Flux, residual gather and RK stage.  mode 0: W_out = L(W_in); mode 1..3:
 // the three stages of the TVD Runge-Kutta scheme from W_in, Wn and dt[inst].
+// partial (nullable, mode 3): each tile's time-step bound of the states
+// written, for launch_cfl of the next step with have_partial.
 template <typename T>
 hipError_t launch_flux(const MeshDev<T>& m, const PhysDev& p, const Schedule& sch, int nvar,
                        int mode, const T* FS, const double* W_in, const double* Wn, double* W_out,
-                       const double* dt, int* flag, const StageTime& tm, hipStream_t st);
+                       const double* dt, int* flag, const StageTime& tm, hipStream_t st,
+                       double* partial = nullptr);
 
 // Per instance k: dt[k] = min(cfl * min_i 1 / sum_p coef_p (|u.n_p| + c),
 // t_end - t[k]) (or min(dt_fixed, t_end - t[k]) if dt_fixed > 0); t may be
-// null (then t = 0).  partial: [n_tq + n_tt].
+// null (then t = 0).  partial: [n_tq + n_tt] per-tile bounds, formed here
+// from W unless have_partial (a flux launch formed them from W already).
 template <typename T>
 hipError_t launch_cfl(const MeshDev<T>& m, const PhysDev& p, int nvar, const double* W, double cfl,
                       double dt_fixed, double t_end, const double* t, double* partial,
-                      double* dt, hipStream_t st);
+                      double* dt, hipStream_t st, bool have_partial = false);
 
 // t[k] += dt[k] for every instance.
 hipError_t launch_advance(int n_inst, double* t, const double* dt, hipStream_t st);

@@ -339,3 +339,55 @@ def test_tile_sizes_fp32_match_oracle(name):
         assert err <= 1e-5
     finally:
         M.tile_size(256)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_multi_step_call_equals_single_steps(prec):
+    """uw_rk3_steps: the last stage of each step forms the next step's CFL
+    bound; the states and times equal those of single-step calls, which
+    form it in a pass of their own, bit for bit (graph replay and eager
+    launches alike)."""
+    import torch
+    uw, mesh, M, T = _setup("mixed")
+    W = _state("mixed", mesh, 17)
+    ph = physics_for(uw, "euler", prec)
+    runs = {}
+    for how in ("single", "multi", "multi-eager"):
+        Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        M.profile(enable=1 if how == "multi-eager" else 0)
+        if how == "single":
+            for _ in range(4):
+                M.rk3_step(ph, Wd, t, cfl=0.5)
+        else:
+            M.rk3_steps(ph, Wd, t, 4, cfl=0.5)
+        M.profile(enable=0)
+        M.check()
+        runs[how] = (Wd.cpu().numpy(), t.item())
+    ref = runs["single"]
+    for how in ("multi", "multi-eager"):
+        assert np.array_equal(runs[how][0], ref[0]), how
+        assert runs[how][1] == ref[1], how
+    assert ref[1] > 0.0
+
+
+def test_graph_cache_keeps_a_bounded_number_of_graphs():
+    """Captured steps are keyed by their arguments; a caller that changes
+    the fixed step every call gets correct results from an evicting cache
+    (at most 8 graphs), equal to eager launches."""
+    import torch
+    uw, mesh, M, T = _setup("tri")
+    W = _state("tri", mesh, 18)
+    ph = physics_for(uw, "euler", "fp64")
+    runs = {}
+    for graph in (True, False):
+        Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        M.profile(enable=0 if graph else 1)
+        for k in range(20):
+            M.rk3_step(ph, Wd, t, dt_fixed=1e-4 * (1 + (k % 11)))
+        M.profile(enable=0)
+        M.check()
+        runs[graph] = (Wd.cpu().numpy(), t.item())
+    assert np.array_equal(runs[True][0], runs[False][0])
+    assert runs[True][1] == runs[False][1]
