@@ -78,15 +78,27 @@ struct DevBuf {
   }
 };
 
-template <class T>
-std::vector<T> convert(const std::vector<double>& v) {
-  if constexpr (std::is_same<T, double>::value) {
-    return v;
-  } else {
-    std::vector<T> o(v.size());
-    for (size_t k = 0; k < v.size(); ++k) o[k] = (T)v[k];
-    return o;
-  }
+// A cell type's [K][R] table (structure of arrays, R rows) in the device
+// layout: rows in chunks of kTableChunk, column c of row r at
+// ((r / kTableChunk) K + c) kTableChunk + r % kTableChunk, converted to T.
+// A lane then reads all columns of its row at constant offsets from one
+// address.  The tail of the last chunk is zero.
+template <class T, class U>
+std::vector<T> chunked(const std::vector<U>& in, int64_t R) {
+  if (R <= 0 || in.empty()) return {};
+  const int64_t C = uw::kTableChunk, K = (int64_t)in.size() / R, nch = (R + C - 1) / C;
+  std::vector<T> out((size_t)(nch * K * C), T(0));
+  uw::parallel_for(nch, uw::default_threads(), [&](int64_t b, int64_t e) {
+    for (int64_t ch = b; ch < e; ++ch) {
+      const int64_t rows = std::min(C, R - ch * C);
+      for (int64_t c = 0; c < K; ++c) {
+        const U* src = in.data() + c * R + ch * C;
+        T* dst = out.data() + (ch * K + c) * C;
+        for (int64_t l = 0; l < rows; ++l) dst[l] = (T)src[l];
+      }
+    }
+  });
+  return out;
 }
 
 // Face tables of the flux kernel from the FP64 face table fgeo [4*3][N]
@@ -139,7 +151,10 @@ struct Staged {
   // per type: the cell each stencil slot s >= 1 reads ([S-1][rows], batch
   // ids), and per instance its first row and first cell of that type
   std::vector<int32_t> q_sid, t_sid;
-  std::vector<int64_t> q_row0, t_row0, q_first, t_first;   // [n_inst + 1] / [n_inst]
+  // rows of each type: instance k's rows start at row0[k] (a multiple of
+  // kTableChunk, so that every wave of a tile reads whole table chunks) and
+  // number nrow[k]
+  std::vector<int64_t> q_row0, t_row0, q_nrow, t_nrow, q_first, t_first;
   std::vector<uw::Tile> tiles;
   std::vector<int32_t> tile_off, tile_ids, inst_tiles, fnb;
   std::vector<double> inflow;   // [n_states][4] prescribed states of all instances
@@ -196,7 +211,7 @@ void retile(Staged& S, int tile) {
     std::vector<std::vector<int32_t>> lists;
     for (int k = 0; k < n; ++k) {
       const int64_t r0 = (q ? S.q_row0 : S.t_row0)[k];
-      const int64_t nk = (q ? S.q_row0 : S.t_row0)[k + 1] - r0;
+      const int64_t nk = (q ? S.q_nrow : S.t_nrow)[k];
       const int64_t first = (q ? S.q_first : S.t_first)[k];
       if (nk > 0)
         uw::build_tile_lists(sid.data(), R, r0, nk, first, Sn, tile, threads, lidx.data(), lists);
@@ -232,8 +247,9 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
   std::vector<int64_t> off(n + 1, 0), qrow(n + 1, 0), trow(n + 1, 0);
   for (int k = 0; k < n; ++k) {
     off[k + 1] = off[k] + ms[k]->N;
-    qrow[k + 1] = qrow[k] + ts[k]->quad.Nt;
-    trow[k + 1] = trow[k] + ts[k]->tri.Nt;
+    const int64_t C = uw::kTableChunk;
+    qrow[k + 1] = (qrow[k] + ts[k]->quad.Nt + C - 1) / C * C;
+    trow[k + 1] = (trow[k] + ts[k]->tri.Nt + C - 1) / C * C;
   }
   S.N = off[n];
   S.rows_q = qrow[n];
@@ -243,7 +259,11 @@ void assemble(const std::vector<const uw::HostMesh*>& ms, const std::vector<cons
   S.t_row0.assign(trow.begin(), trow.end());
   S.q_first.resize(n);
   S.t_first.resize(n);
+  S.q_nrow.resize(n);
+  S.t_nrow.resize(n);
   for (int k = 0; k < n; ++k) {
+    S.q_nrow[k] = ts[k]->quad.Nt;
+    S.t_nrow[k] = ts[k]->tri.Nt;
     S.q_first[k] = off[k] + ts[k]->quad.first;
     S.t_first[k] = off[k] + ts[k]->tri.first;
   }
@@ -409,18 +429,19 @@ uw_status ensure_tables(Engine& E) {
   up(d.tile_off, S.tile_off);
   up(d.tile_ids, S.tile_ids);
   up(d.inst_tiles, S.inst_tiles);
-  up(d.q_li, S.q_lidx);
-  up(d.q_Y, convert<T>(S.q_Y));
-  up(d.q_off, convert<T>(S.q_off));
-  up(d.q_gam, convert<T>(S.q_gam));
-  up(d.q_sig, convert<T>(S.q_sig));
-  up(d.q_eta, convert<T>(S.q_eta));
-  up(d.t_li, S.t_lidx);
-  up(d.t_Y, convert<T>(S.t_Y));
-  up(d.t_off, convert<T>(S.t_off));
-  up(d.t_gam, convert<T>(S.t_gam));
-  up(d.t_sig, convert<T>(S.t_sig));
-  up(d.t_eta, convert<T>(S.t_eta));
+  const int64_t Rq = S.rows_q, Rt = S.rows_t;
+  up(d.q_li, chunked<uint16_t>(S.q_lidx, Rq));
+  up(d.q_Y, chunked<T>(S.q_Y, Rq));
+  up(d.q_off, chunked<T>(S.q_off, Rq));
+  up(d.q_gam, chunked<T>(S.q_gam, Rq));
+  up(d.q_sig, chunked<T>(S.q_sig, Rq));
+  up(d.q_eta, chunked<T>(S.q_eta, Rq));
+  up(d.t_li, chunked<uint16_t>(S.t_lidx, Rt));
+  up(d.t_Y, chunked<T>(S.t_Y, Rt));
+  up(d.t_off, chunked<T>(S.t_off, Rt));
+  up(d.t_gam, chunked<T>(S.t_gam, Rt));
+  up(d.t_sig, chunked<T>(S.t_sig, Rt));
+  up(d.t_eta, chunked<T>(S.t_eta, Rt));
   up(d.fnb, S.fnb);
   if (!S.inflow.empty()) up(d.inflow, S.inflow);
   if (!S.ff_front.empty()) {

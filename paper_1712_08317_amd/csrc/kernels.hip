@@ -209,15 +209,16 @@ struct WenoIn {
 };
 
 template <typename T, int NF>
-__device__ inline void weno_load(const TypeDev<T>& td, int64_t r, WenoIn<T, NF>& in) {
+__device__ inline void weno_load(const TypeDev<T>& td, RowRef r, WenoIn<T, NF>& in) {
   using L = Layout<NF>;
-  const int64_t n = td.Nt;
+  const uint16_t* lr = table_row<L::S>(td.lidx, r);
+  const T* yr = table_row<L::M * 4>(td.Y, r);
 #pragma unroll
-  for (int s = 0; s < L::S; ++s) in.li[s] = td.lidx[s * n + r];
+  for (int s = 0; s < L::S; ++s) in.li[s] = lr[s * kTableChunk];
 #pragma unroll
   for (int j = 0; j < L::M; ++j)
 #pragma unroll
-    for (int k = 0; k < 4; ++k) in.Y[j][k] = td.Y[(j * 4 + k) * n + r];
+    for (int k = 0; k < 4; ++k) in.Y[j][k] = yr[(j * 4 + k) * kTableChunk];
 }
 
 // Normalised split weights of one Gauss point (Sec. 3.4) from the stored
@@ -236,24 +237,28 @@ __device__ inline void split_weights(const T (&h)[M], T theta, T ratio, T (&gp)[
 
 // WENO point values of one cell at its 2n Gauss points (paper Sec. 3.4).
 template <typename T, int NF, int V>
-__device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
+__device__ inline void weno_cell(const TypeDev<T>& td, RowRef r, const WenoIn<T, NF>& in,
                                  const double* lds, int len, const MeshDev<T>& m, int64_t i,
                                  T* fs, T eps, T theta) {
   using L = Layout<NF>;
-  constexpr int S = L::S, M = L::M, G = 2 * NF;
-  const int64_t n = td.Nt;
+  constexpr int S = L::S, M = L::M, G = 2 * NF, C = kTableChunk;
+  const uint16_t* lr = table_row<S>(td.lidx, r);
+  const T* yr = table_row<M * 4>(td.Y, r);
+  const T* offr = table_row<2 * G>(td.off, r);
+  const T* sigr = table_row<3 * G>(td.sig, r);
+  const T* gamr = table_row<G * M>(td.gam, r);
   // Each Gauss point's offsets and weights are fetched one point ahead.
   // Measured on gfx950: the quadrilateral kernels then spill a few values
   // (24 bytes per lane in FP32, 12 in FP64) and still run 4% (FP32) and 30%
   // (FP64) faster than with the loads at the point itself, where the FP64
   // kernel, at one wave per SIMD, waited for each weight's load in turn.
-  T ga_n[M], ox_n = td.off[r], oy_n = td.off[n + r];
-  T s0_n = td.sig[r], s1_n = td.sig[n + r], s2_n = td.sig[2 * n + r];
+  T ga_n[M], ox_n = offr[0], oy_n = offr[C];
+  T s0_n = sigr[0], s1_n = sigr[C], s2_n = sigr[2 * C];
 #pragma unroll
-  for (int j = 0; j < M; ++j) ga_n[j] = td.gam[j * n + r];
+  for (int j = 0; j < M; ++j) ga_n[j] = gamr[j * C];
   // per-cell inputs: prefetched, or read here
-  auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)td.lidx[s * n + r]; };
-  auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : td.Y[(j * 4 + k) * n + r]; };
+  auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)lr[s * C]; };
+  auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : yr[(j * 4 + k) * C]; };
   double w0[V];
   const int l0 = li(0);
 #pragma unroll
@@ -288,13 +293,13 @@ __device__ inline void weno_cell(const TypeDev<T>& td, int64_t r, const WenoIn<T
 #pragma unroll
     for (int j = 0; j < M; ++j) ga[j] = ga_n[j];
     if (g + 1 < G) {
-      ox_n = td.off[(2 * g + 2) * n + r];
-      oy_n = td.off[(2 * g + 3) * n + r];
-      s0_n = td.sig[(3 * g + 3) * n + r];
-      s1_n = td.sig[(3 * g + 4) * n + r];
-      s2_n = td.sig[(3 * g + 5) * n + r];
+      ox_n = offr[(2 * g + 2) * C];
+      oy_n = offr[(2 * g + 3) * C];
+      s0_n = sigr[(3 * g + 3) * C];
+      s1_n = sigr[(3 * g + 4) * C];
+      s2_n = sigr[(3 * g + 5) * C];
 #pragma unroll
-      for (int j = 0; j < M; ++j) ga_n[j] = td.gam[((g + 1) * M + j) * n + r];
+      for (int j = 0; j < M; ++j) ga_n[j] = gamr[((g + 1) * M + j) * C];
     }
     T gp[M], gm[M];
     split_weights<T, M>(ga, theta, ratio, gp, gm);
@@ -367,14 +372,18 @@ __device__ inline void roe_eigen(const T* WA, const T* WB, T nx, T ny, T gam, T 
 // indicators and nonlinear weights are formed per field, and the two Gauss
 // points of the face are projected back.
 template <typename T, int NF>
-__device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const WenoIn<T, NF>& in,
+__device__ inline void weno_cell_char(const TypeDev<T>& td, RowRef r, const WenoIn<T, NF>& in,
                                       const double* lds, int len, const MeshDev<T>& m,
                                       int64_t i, T* fs, T eps, T theta, T gam) {
   using L = Layout<NF>;
-  constexpr int S = L::S, M = L::M, V = 4;
-  const int64_t n = td.Nt;
-  auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)td.lidx[s * n + r]; };
-  auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : td.Y[(j * 4 + k) * n + r]; };
+  constexpr int S = L::S, M = L::M, V = 4, G = 2 * NF, C = kTableChunk;
+  const uint16_t* lr = table_row<S>(td.lidx, r);
+  const T* yr = table_row<M * 4>(td.Y, r);
+  const T* offr = table_row<2 * G>(td.off, r);
+  const T* sigr = table_row<3 * G>(td.sig, r);
+  const T* gamr = table_row<G * M>(td.gam, r);
+  auto li = [&](int s) { return kPrefetch<NF> ? in.li[s] : (int)lr[s * C]; };
+  auto Y = [&](int j, int k) { return kPrefetch<NF> ? in.Y[j][k] : yr[(j * 4 + k) * C]; };
   double w0[V];
   const int l0 = li(0);
 #pragma unroll
@@ -409,7 +418,7 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
       // face neighbour: slot k + 1 (read again per face: indexing the
       // prefetched slot list with the loop counter would place it in
       // private memory)
-      const int l = td.lidx[(k + 1) * n + r];
+      const int l = lr[(k + 1) * C];
 #pragma unroll
       for (int v = 0; v < V; ++v) Wk[v] = (T)lds[v * len + l];
     }
@@ -419,14 +428,14 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const int g = 2 * k + q;
-      ox[q] = td.off[(2 * g) * n + r];
-      oy[q] = td.off[(2 * g + 1) * n + r];
-      sp[q] = td.sig[(3 * g) * n + r];
-      sm[q] = td.sig[(3 * g + 1) * n + r];
+      ox[q] = offr[(2 * g) * C];
+      oy[q] = offr[(2 * g + 1) * C];
+      sp[q] = sigr[(3 * g) * C];
+      sm[q] = sigr[(3 * g + 1) * C];
       T h[M];
 #pragma unroll
-      for (int j = 0; j < M; ++j) h[j] = td.gam[(g * M + j) * n + r];
-      split_weights<T, M>(h, theta, td.sig[(3 * g + 2) * n + r], gp[q], gm[q]);
+      for (int j = 0; j < M; ++j) h[j] = gamr[(g * M + j) * C];
+      split_weights<T, M>(h, theta, sigr[(3 * g + 2) * C], gp[q], gm[q]);
     }
     T inc[2][V];   // reconstructed increments per field at the two points
 #pragma unroll
@@ -481,19 +490,20 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, int64_t r, const Wen
 
 // Point values of the quadratic P^2 (eq. (polynomial-eta)): the linear scheme.
 template <typename T, int NF, int V>
-__device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double* lds, int len,
+__device__ inline void linear_cell(const TypeDev<T>& td, RowRef r, const double* lds, int len,
                                    const MeshDev<T>& m, int64_t i, T* fs) {
   using L = Layout<NF>;
-  constexpr int S = L::S, G = 2 * NF;
-  const int64_t n = td.Nt;
+  constexpr int S = L::S, G = 2 * NF, C = kTableChunk;
+  const uint16_t* lr = table_row<S>(td.lidx, r);
+  const T* etar = table_row<G * (S - 1)>(td.eta, r);
   double w0[V];
-  const int l0 = td.lidx[r];
+  const int l0 = lr[0];
 #pragma unroll
   for (int v = 0; v < V; ++v) w0[v] = lds[v * len + l0];
   T dW[S - 1][V];
 #pragma unroll
   for (int s = 0; s < S - 1; ++s) {
-    const int l = td.lidx[(s + 1) * n + r];
+    const int l = lr[(s + 1) * C];
 #pragma unroll
     for (int v = 0; v < V; ++v) dW[s][v] = (T)(lds[v * len + l] - w0[v]);
   }
@@ -505,7 +515,7 @@ __device__ inline void linear_cell(const TypeDev<T>& td, int64_t r, const double
     for (int v = 0; v < V; ++v) acc[v] = 0;
 #pragma unroll
     for (int s = 0; s < S - 1; ++s) {
-      const T e = td.eta[(g * (S - 1) + s) * n + r];
+      const T e = etar[(g * (S - 1) + s) * C];
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] += e * dW[s][v];
     }
@@ -542,11 +552,14 @@ __global__ __launch_bounds__(TILE, (kReconBlocksPerCu<T, NF, KIND, TILE>)) void 
   constexpr int REC = 8 * V;              // face-state values per cell
   constexpr int PER = 16 / sizeof(T);     // values per 16-byte unit
   constexpr int STRIDE = REC + PER;       // LDS row per cell, padded against bank conflicts
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kTableChunk;
   for (int k = blockIdx.x; k < nt; k += gridDim.x) {
     const int tile = t0 + k;
     const Tile tl = m.tiles[tile];
     const bool act = (int)threadIdx.x < tl.count;
-    const int64_t r = tl.row0 + threadIdx.x;
+    // rows of a tile start at a multiple of kTableChunk: each wave reads
+    // whole chunks of the tables
+    const RowRef r{tl.row0 / kTableChunk + wave, threadIdx.x % kTableChunk};
     WenoIn<T, NF> in;
     if (KIND != 1 && kPrefetch<NF> && act) weno_load<T, NF>(td, r, in);
     const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);

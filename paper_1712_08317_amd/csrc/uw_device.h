@@ -21,7 +21,14 @@ struct Tile {
   int32_t inst;    // mesh instance
 };
 
-// Rows of one cell type, structure of arrays [k][Nt].
+// Per-cell tables of one cell type.  A table of K columns ([K][Nt] below)
+// is stored in chunks of kTableChunk rows: column c of row r at
+// ((r / kTableChunk) K + c) kTableChunk + r % kTableChunk.  A lane forms
+// its row's address once (table_row) and reads column c at the constant
+// offset c kTableChunk, which the loads take as an immediate, instead of
+// one base address per column.
+constexpr int kTableChunk = 64;
+
 template <typename T>
 struct TypeDev {
   int64_t Nt = 0;
@@ -32,6 +39,20 @@ struct TypeDev {
   const T* sig = nullptr;           // [2n*3][Nt] sigma+, sigma-, sigma+/sigma- of the split
   const T* eta = nullptr;           // [2n*(S-1)][Nt] point-value coefficients (linear mode)
 };
+
+// A lane's row of the tables: its wave's chunk (the same for every lane of
+// the wave) and its place in the chunk.
+struct RowRef {
+  int64_t chunk;
+  uint32_t lane;
+};
+
+// Column 0 of a lane's row of a chunked table of K columns: the chunk's
+// start is wave-uniform (scalar registers), the lane adds a 32-bit offset.
+template <int K, typename P>
+__device__ inline P* table_row(P* base, RowRef r) {
+  return (base + r.chunk * (int64_t)(K * kTableChunk)) + r.lane;
+}
 
 // Boundary codes of face tables (fnb): -1 transmissive, -2 reflective,
 // -3 - s prescribed state s, kFrontCode - j front face j.
