@@ -291,9 +291,10 @@ uw_status uw_batch_rk3_step(uw_batch* batch, double* W, double cfl, double dt_fi
 /* Chooses the tile size (256 or 512 cells; 512 only for FP32 WENO on the
  * conserved variables) and the launch schedule (number of persistent blocks
  * of the reconstruction kernels of each cell type and of the flux kernel:
- * one block per tile, or 1, 2, 4 or 8 blocks per compute unit) by timing
- * residual evaluations on the mesh or batch (exactly one of them) and
- * stores both there.  `cache_path` (nullable): a text file of earlier
+ * one block per tile, or 1, 2, 4 or 8 blocks per compute unit; or one
+ * reconstruction launch for both cell types) by timing residual
+ * evaluations on the mesh or batch (exactly one of them) and stores both
+ * there.  `cache_path` (nullable): a text file of earlier
  * choices keyed by the workload's shape, read first and appended to. */
 uw_status uw_autotune(uw_mesh* mesh, uw_batch* batch, const uw_physics* physics,
                       const char* cache_path, void* stream);
@@ -301,7 +302,11 @@ uw_status uw_autotune(uw_mesh* mesh, uw_batch* batch, const uw_physics* physics,
 /* Reads (get, nullable, host [3]) and/or sets (set, nullable) the launch
  * schedule of a mesh or batch (exactly one): persistent blocks of the
  * quadrilateral reconstruction, of the triangle reconstruction and of the
- * flux kernel; 0 = one block per tile.  Set is applied before get. */
+ * flux kernel; 0 = one block per tile.  A triangle entry of -1 puts both
+ * cell types in one reconstruction launch of the quadrilateral entry's
+ * blocks (not for the FP32 linear scheme, whose two kernels differ in
+ * occupancy: there it means separate launches of one block per tile).
+ * Other negative entries: UW_EINVAL.  Set is applied before get. */
 uw_status uw_schedule(uw_mesh* mesh, uw_batch* batch, int32_t* get, const int32_t* set);
 
 /* Tile size of a mesh or batch (exactly one): cells per tile, i.e. threads

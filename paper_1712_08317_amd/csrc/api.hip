@@ -1108,7 +1108,7 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
                         &c6, &rq, &rt, &fl, &tl) == 11) {
           char k2[200];
           std::snprintf(k2, sizeof(k2), "%lld %d %d %d %d %d %d", a, c1, c2, c3, c4, c5, c6);
-          if (std::strcmp(k2, key) == 0 && rq >= 0 && rt >= 0 && fl >= 0 &&
+          if (std::strcmp(k2, key) == 0 && rq >= 0 && rt >= -1 && fl >= 0 &&
               uw::tile_size_ok(tl)) {
             E.sched = uw::Schedule{rq, rt, fl};
             tile_found = tl;
@@ -1191,6 +1191,7 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
       UW_HIP(hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, E.device));
       if (need > (size_t)lim) continue;
     }
+    if (E.sched.recon_t < 0) E.sched.recon_t = 0;   // separate launches first
     for (int knob = 0; knob < 3 && s == UW_OK; ++knob) {
       int* val = knob == 0 ? &E.sched.recon_q : knob == 1 ? &E.sched.recon_t : &E.sched.flux;
       int best_v = *val;
@@ -1210,6 +1211,28 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
     float ms = 0.0f;
     if (s == UW_OK) s = time_residual(&ms);
     if (s != UW_OK) break;
+    // both cell types in one reconstruction launch (recon_t = -1), where
+    // both types are present and the two kernels share launch bounds
+    const bool mergeable = E.staged.n_tq > 0 && E.staged.n_tt > 0 &&
+                           (p->precision == UW_FP64 || E.scheme.mode != 1);
+    if (mergeable) {
+      const uw::Schedule sep = E.sched;
+      float best_m = ms;
+      uw::Schedule best_ms = sep;
+      for (int c : mult) {
+        E.sched = uw::Schedule{c * cus, -1, sep.flux};
+        float mm = 0.0f;
+        s = time_residual(&mm);
+        if (s != UW_OK) break;
+        if (mm < best_m) {
+          best_m = mm;
+          best_ms = E.sched;
+        }
+      }
+      if (s != UW_OK) break;
+      E.sched = best_ms;
+      ms = best_m;
+    }
     if (ms < best_all) {
       best_all = ms;
       best_tile = tile;
@@ -1248,8 +1271,8 @@ uw_status uw_schedule(uw_mesh* m, uw_batch* b, int32_t* get, const int32_t* set)
   if ((!m) == (!b)) return fail(UW_EINVAL, "give exactly one of a mesh or a batch");
   Engine& E = m ? m->eng : b->eng;
   if (set) {
-    for (int k = 0; k < 3; ++k)
-      if (set[k] < 0) return fail(UW_EINVAL, "schedule entries must be >= 0");
+    if (set[0] < 0 || set[1] < -1 || set[2] < 0)
+      return fail(UW_EINVAL, "schedule entries must be >= 0 (the second >= -1)");
     E.sched = uw::Schedule{set[0], set[1], set[2]};
     E.clear_graphs();
   }

@@ -541,49 +541,73 @@ __device__ inline void linear_cell(const TypeDev<T>& td, RowRef r, const double*
 template <typename T, int NF, int KIND, int TILE>
 constexpr int kReconBlocksPerCu = (sizeof(T) == 4 && (NF == 3 || KIND != 1) ? 2 : 1) * 256 / TILE;
 
-template <typename T, int NF, int V, int KIND, int TILE>
-__global__ __launch_bounds__(TILE, (kReconBlocksPerCu<T, NF, KIND, TILE>)) void k_recon(
-    const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
-  extern __shared__ double lds[];
+// One tile of cell type NF: stage its stencil values, reconstruct each
+// cell's Gauss-point states into LDS, write the tile's records out.
+template <typename T, int NF, int V, int KIND>
+__device__ inline void recon_tile(const double* __restrict__ W, const MeshDev<T>& m,
+                                  T* __restrict__ FS, T eps, T theta, T gam, int tile, int wave,
+                                  double* lds) {
   const TypeDev<T>& td = NF == 4 ? m.quad : m.tri;
-  const int t0 = NF == 4 ? 0 : m.n_tq, nt = NF == 4 ? m.n_tq : m.n_tt;
   const int maxlen = NF == 4 ? m.max_len_q : m.max_len_t;
   T* fs_lds = reinterpret_cast<T*>(lds + ((maxlen * V + 1) & ~1));
   constexpr int REC = 8 * V;              // face-state values per cell
   constexpr int PER = 16 / sizeof(T);     // values per 16-byte unit
   constexpr int STRIDE = REC + PER;       // LDS row per cell, padded against bank conflicts
+  const Tile tl = m.tiles[tile];
+  const bool act = (int)threadIdx.x < tl.count;
+  // rows of a tile start at a multiple of kTableChunk: each wave reads
+  // whole chunks of the tables
+  const RowRef r{tl.row0 / kTableChunk + wave, threadIdx.x % kTableChunk};
+  WenoIn<T, NF> in;
+  if (KIND != 1 && kPrefetch<NF> && act) weno_load<T, NF>(td, r, in);
+  const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);
+  if (act) {
+    T* fs = fs_lds + threadIdx.x * STRIDE;
+    if constexpr (KIND == 1) {
+      linear_cell<T, NF, V>(td, r, lds, len, m, tl.first + threadIdx.x, fs);
+    } else if constexpr (KIND == 2 && V == 4) {
+      weno_cell_char<T, NF>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta, gam);
+    } else {
+      weno_cell<T, NF, V>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta);
+    }
+  }
+  __syncthreads();
+  // the tile's face states are contiguous in FS: copy them in 16-byte units
+  constexpr int U = REC / PER;            // 16-byte units per cell
+  const int n16 = tl.count * U;
+  int4* dst = reinterpret_cast<int4*>(FS + (int64_t)tl.first * REC);
+  for (int q = threadIdx.x; q < n16; q += blockDim.x) {
+    const int c = q / U, u = q - c * U;
+    dst[q] = *reinterpret_cast<const int4*>(fs_lds + c * STRIDE + u * PER);
+  }
+  __syncthreads();   // the next tile overwrites both LDS regions
+}
+
+template <typename T, int NF, int V, int KIND, int TILE>
+__global__ __launch_bounds__(TILE, (kReconBlocksPerCu<T, NF, KIND, TILE>)) void k_recon(
+    const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
+  extern __shared__ double lds[];
+  const int t0 = NF == 4 ? 0 : m.n_tq, nt = NF == 4 ? m.n_tq : m.n_tt;
   const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kTableChunk;
+  for (int k = blockIdx.x; k < nt; k += gridDim.x)
+    recon_tile<T, NF, V, KIND>(W, m, FS, eps, theta, gam, t0 + k, wave, lds);
+}
+
+// Both cell types in one launch: block b takes tiles b, b + gridDim.x, ...
+// of the quadrilateral tiles followed by the triangle ones (for kinds whose
+// two kernels share their launch bounds).
+template <typename T, int V, int KIND, int TILE>
+__global__ __launch_bounds__(TILE, (kReconBlocksPerCu<T, 4, KIND, TILE>)) void k_recon_both(
+    const double* __restrict__ W, MeshDev<T> m, T* __restrict__ FS, T eps, T theta, T gam) {
+  static_assert(kReconBlocksPerCu<T, 4, KIND, TILE> == kReconBlocksPerCu<T, 3, KIND, TILE>);
+  extern __shared__ double lds[];
+  const int wave = __builtin_amdgcn_readfirstlane((int)threadIdx.x) / kTableChunk;
+  const int nt = m.n_tq + m.n_tt;
   for (int k = blockIdx.x; k < nt; k += gridDim.x) {
-    const int tile = t0 + k;
-    const Tile tl = m.tiles[tile];
-    const bool act = (int)threadIdx.x < tl.count;
-    // rows of a tile start at a multiple of kTableChunk: each wave reads
-    // whole chunks of the tables
-    const RowRef r{tl.row0 / kTableChunk + wave, threadIdx.x % kTableChunk};
-    WenoIn<T, NF> in;
-    if (KIND != 1 && kPrefetch<NF> && act) weno_load<T, NF>(td, r, in);
-    const int len = stage_tile<V>(W, m.N, m.tile_off, m.tile_ids, tile, lds);
-    if (act) {
-      T* fs = fs_lds + threadIdx.x * STRIDE;
-      if constexpr (KIND == 1) {
-        linear_cell<T, NF, V>(td, r, lds, len, m, tl.first + threadIdx.x, fs);
-      } else if constexpr (KIND == 2 && V == 4) {
-        weno_cell_char<T, NF>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta,
-                              gam);
-      } else {
-        weno_cell<T, NF, V>(td, r, in, lds, len, m, tl.first + threadIdx.x, fs, eps, theta);
-      }
-    }
-    __syncthreads();
-    // the tile's face states are contiguous in FS: copy them in 16-byte units
-    constexpr int U = REC / PER;            // 16-byte units per cell
-    const int n16 = tl.count * U;
-    int4* dst = reinterpret_cast<int4*>(FS + (int64_t)tl.first * REC);
-    for (int q = threadIdx.x; q < n16; q += blockDim.x) {
-      const int c = q / U, u = q - c * U;
-      dst[q] = *reinterpret_cast<const int4*>(fs_lds + c * STRIDE + u * PER);
-    }
-    __syncthreads();   // the next tile overwrites both LDS regions
+    if (k < m.n_tq)
+      recon_tile<T, 4, V, KIND>(W, m, FS, eps, theta, gam, k, wave, lds);
+    else
+      recon_tile<T, 3, V, KIND>(W, m, FS, eps, theta, gam, k, wave, lds);
   }
 }
 
@@ -963,6 +987,41 @@ hipError_t launch_recon(const MeshDev<T>& m0, const SchemeDev& s, const PhysDev&
     }
     return hipGetLastError();
   };
+  // recon_t < 0: both types in one launch of recon_q blocks, where the two
+  // kernels share their launch bounds (every kind but the FP32 linear one)
+  if (sch.recon_t < 0 && m.n_tq > 0 && m.n_tt > 0 && (sizeof(T) == 8 || kind != 1)) {
+    const int ntiles = m.n_tq + m.n_tt;
+    const unsigned grid = (unsigned)(sch.recon_q > 0 && sch.recon_q < ntiles ? sch.recon_q : ntiles);
+    const size_t shm = std::max(recon_lds<T>(m.max_len_q, nvar, m.tile),
+                                recon_lds<T>(m.max_len_t, nvar, m.tile));
+    if (shm > lds_limit()) return hipErrorInvalidConfiguration;
+    auto go = [&](auto v_tag, auto kind_tag, auto tile_tag) {
+      constexpr int V = decltype(v_tag)::value, K = decltype(kind_tag)::value;
+      constexpr int TL = decltype(tile_tag)::value;
+      if constexpr (sizeof(T) == 8 || K != 1)
+        k_recon_both<T, V, K, TL><<<grid, TL, shm, st>>>(W, m, FS, eps, th, gam);
+    };
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using I4 = std::integral_constant<int, 4>;
+    using T256 = std::integral_constant<int, 256>;
+    if (kind == 1) {
+      if (nvar == 4) go(I4{}, I1{}, T256{});
+      else go(I1{}, I1{}, T256{});
+    } else if (kind == 2) {
+      go(I4{}, std::integral_constant<int, 2>{}, T256{});
+    } else {
+      auto by_tile = [&](auto v_tag) {
+        if constexpr (sizeof(T) == 4) {
+          if (m.tile == 512) return go(v_tag, I0{}, std::integral_constant<int, 512>{});
+        }
+        go(v_tag, I0{}, T256{});
+      };
+      if (nvar == 4) by_tile(I4{});
+      else by_tile(I1{});
+    }
+    return hipGetLastError();
+  }
   hipError_t e = one(m.n_tq, m.max_len_q, sch.recon_q, std::integral_constant<int, 4>{});
   if (e != hipSuccess) return e;
   return one(m.n_tt, m.max_len_t, sch.recon_t, std::integral_constant<int, 3>{});

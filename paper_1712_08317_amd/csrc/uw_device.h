@@ -104,7 +104,8 @@ struct SchemeDev {
 };
 
 // Launch shape: number of persistent blocks of each kernel (0 = one block
-// per tile).
+// per tile); recon_t = -1: both cell types in one reconstruction launch of
+// recon_q blocks.
 struct Schedule {
   int recon_q = 0, recon_t = 0, flux = 0;
 };

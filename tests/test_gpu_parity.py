@@ -391,3 +391,36 @@ def test_graph_cache_keeps_a_bounded_number_of_graphs():
         runs[graph] = (Wd.cpu().numpy(), t.item())
     assert np.array_equal(runs[True][0], runs[False][0])
     assert runs[True][1] == runs[False][1]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("scheme,tile", [("weno", 256), ("weno", 512), ("linear", 256),
+                                         ("characteristic", 256)])
+def test_one_reconstruction_launch_for_both_cell_types(prec, scheme, tile):
+    """Schedule (q, -1, f): both cell types reconstructed by one launch (any
+    number of persistent blocks, each taking quadrilateral and triangle
+    tiles) give the residual of the separate launches bit for bit; the FP32
+    linear scheme, whose two kernels differ in occupancy, keeps separate
+    launches."""
+    if tile == 512 and (prec != "fp32" or scheme != "weno"):
+        pytest.skip("512-cell tiles: FP32 WENO on the conserved variables only")
+    import paper_1712_08317_amd as uw
+    for name in ("mixed", "sod"):
+        mesh = MESHES[name]
+        M = uw.Mesh.from_workload(mesh, device=0)
+        M.precompute(uw.make_scheme(
+            mode=uw.UW_LINEAR if scheme == "linear" else uw.UW_WENO,
+            variables=uw.UW_CHARACTERISTIC if scheme == "characteristic" else uw.UW_CONSERVED))
+        if tile != 256:
+            assert M.tile_size(tile) == tile
+        W = wl.seeded_state(mesh, 4, 23) if not (name == "sod" and scheme == "linear") \
+            else wl.initial_state("c3", mesh)
+        M.schedule((0, 0, 0))
+        ref = gpu_residual(uw, M, W, "euler", prec)
+        for q in (0, 2, 256):
+            assert M.schedule((q, -1, 0)) == (q, -1, 0)
+            got = gpu_residual(uw, M, W, "euler", prec)
+            assert np.array_equal(got, ref), (name, q)
+        with pytest.raises(uw.UwError) as e:
+            M.schedule((0, -2, 0))
+        assert e.value.status == uw.UW_EINVAL
