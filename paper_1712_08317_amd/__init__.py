@@ -316,8 +316,10 @@ class Mesh:
         _check(LIB.uw_check(self.handle, None, _stream(stream)))
 
     def schedule(self, set_to=None):
-        """The launch schedule (recon quads, recon triangles, flux); 0 = one
-        block per tile.  ``set_to`` (3 ints) replaces it first."""
+        """The launch schedule (recon quads, recon triangles, flux): persistent
+        blocks, 0 = one block per tile; a triangle entry of -1 reconstructs
+        both cell types in one launch.  ``set_to`` (3 ints) replaces it
+        first."""
         got = np.zeros(3, dtype=np.int32)
         s = None if set_to is None else np.ascontiguousarray(set_to, dtype=np.int32)
         _check(LIB.uw_schedule(self.handle, None, got.ctypes.data,
