@@ -1,7 +1,10 @@
-"""The GPU scheme against the physics rather than the oracle: the rotated
-shock tube (the paper's one-dimensional Riemann problem of Sec. 4, turned
-by 30 degrees on a mixed mesh) against the exact Riemann solution."""
+"""The GPU scheme against the physics: the rotated shock tube (the paper's
+one-dimensional Riemann problem of Sec. 4, turned by 30 degrees on a mixed
+mesh) against the exact Riemann solution, and the paper's own Sod and Lax
+set-ups at their end times against the oracle's stored solutions and the
+exact one."""
 import math
+import os
 
 import numpy as np
 import pytest
@@ -70,3 +73,68 @@ def test_rotated_shock_tube_converges_to_the_exact_solution(variables, band, siz
     print(variables, band, sizes, e1, e2, flush=True)
     assert e1[0] < 0.03 and e1[1] < 0.06
     assert e2[0] < 0.8 * e1[0] and e2[1] < 0.8 * e1[1]
+
+
+# The paper's own one-dimensional Riemann set-up (Sec. 4.2): [0,1] x [0,0.5],
+# h = 1/100, open boundaries, Sod to t = 0.2 and Lax to t = 0.16.  The
+# oracle's centre-line solutions are stored under tests/golden (written by
+# make_riemann_1d.py, which calls only the oracle).
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+RIEMANN_CASES = {   # name: (problem, split, jitter, L1 density bound against the exact solution)
+    "sod_quad": ("sod", "quad", 0.0, 0.010),
+    "sod_quad_irregular": ("sod", "quad", 0.2, 0.010),
+    "sod_tri": ("sod", "tri", 0.0, 0.009),
+    "lax_quad": ("lax", "quad", 0.0, 0.030),
+    "lax_quad_irregular": ("lax", "quad", 0.2, 0.030),
+    "lax_tri": ("lax", "tri", 0.0, 0.030),
+}
+
+
+def _riemann_golden(name):
+    path = os.path.join(GOLD, f"riemann_1d_{name}.txt")
+    steps = None
+    for line in open(path):
+        if line.startswith("# steps"):
+            steps = int(line.split()[2])
+    data = np.loadtxt(path, comments="#")
+    return data[:, 0].astype(np.int64), data[:, 1:3], data[:, 3:6], steps
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("name", list(RIEMANN_CASES))
+def test_paper_riemann_problems_at_their_end_times(name, prec):
+    """Each case runs to its end time on the device (CFL 0.5, the device's
+    time-step rule, admissibility checked every call); along the centre line
+    the solution matches the oracle's element by element, and its density
+    is within the case's L1 bound of the exact solution."""
+    import torch
+    import paper_1712_08317_amd as uw
+    problem, split, jitter, bound = RIEMANN_CASES[name]
+    idx, xy, ref, steps_ref = _riemann_golden(name)
+    mesh, W, t_end = wl.riemann_1d(problem, 100, split, jitter)
+    M = uw.Mesh.from_workload(mesh, device=0)
+    M.precompute()
+    Wd = torch.from_numpy(M.to_internal(W)).to("cuda:0")
+    t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+    ph = physics_for(uw, "euler", prec)
+    calls = 0
+    while float(t.cpu()[0]) < t_end - 1e-12 and calls < 100:
+        M.rk3_steps(ph, Wd, t, 20, cfl=0.5, t_end=t_end)
+        M.check()
+        calls += 1
+    assert abs(float(t.cpu()[0]) - t_end) < 1e-12
+    Wh = M.to_original(Wd.cpu().numpy())
+    rho = Wh[0, idx]
+    u = Wh[1, idx] / rho
+    v = Wh[2, idx] / rho
+    p = (wl.GAMMA - 1.0) * (Wh[3, idx] - 0.5 * rho * (u * u + v * v))
+    got = np.stack([rho, u, p], axis=1)
+    err = np.abs(got - ref).max(axis=0)
+    left, right, _ = wl.RIEMANN_1D[problem]
+    rho_x, _, _ = er.sample(left, right, (xy[:, 0] - 0.5) / t_end)
+    l1 = float(np.abs(rho - rho_x).mean())
+    print(name, prec, "max |device - oracle| (rho, u, p):", err, "L1 rho vs exact:", l1,
+          "oracle steps:", steps_ref, flush=True)
+    tol = 2e-5 if prec == "fp32" else 1e-10
+    assert (err <= tol).all(), err
+    assert l1 <= bound

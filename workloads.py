@@ -442,6 +442,34 @@ def lax_state(mesh: Mesh, gamma=GAMMA) -> np.ndarray:
     return primitive_to_conserved(rho, u, np.zeros_like(u), p, gamma)
 
 
+RIEMANN_1D = {   # (rho, u, p) left and right, end time (Sec. 4.2)
+    "sod": ((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), 0.2),
+    "lax": ((0.445, 0.698, 3.528), (0.5, 0.0, 0.571), 0.16),
+}
+
+
+def riemann_1d(problem: str = "sod", n: int = 100, split="quad", jitter: float = 0.0,
+               seed: int = 7, gamma=GAMMA):
+    """One-dimensional Riemann problem as the paper sets it (Sec. 4.2): the
+    states of RIEMANN_1D split at x = 0.5 on [0,1] x [0,0.5], h = 1/n, open
+    (transmissive) boundaries.  ``split``: "quad", "tri" (split squares,
+    jittered by ``jitter``) or "lattice" (near-equilateral triangles).
+    Returns (mesh, state, end time); cells take the state at their vertex
+    average."""
+    left, right, t_end = RIEMANN_1D[problem]
+    if split == "lattice":
+        mesh = lattice_mesh(n, int(round(0.5 * n / (math.sqrt(3.0) / 2))), 1.0, 0.5,
+                            name=f"{problem}-lattice{n}")
+    else:
+        mesh = grid_mesh(n, n // 2, 1.0, 0.5, split, jitter, seed, False,
+                         name=f"{problem}-{split}{n}")
+    cx, _ = cell_centres(mesh)
+    lft = cx < 0.5
+    W = primitive_to_conserved(np.where(lft, left[0], right[0]), np.where(lft, left[1], right[1]),
+                               np.zeros_like(cx), np.where(lft, left[2], right[2]), gamma)
+    return mesh, W, t_end
+
+
 def shu_osher(nx: int = 400, ny: int = 10, jitter: float = 0.3, seed: int = 11,
               split="quad", gamma=GAMMA):
     """Shu-Osher problem as the paper sets it (Sec. 4.2): [0,10] x [0,0.25],
