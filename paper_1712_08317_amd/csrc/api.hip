@@ -1093,21 +1093,22 @@ uw_status uw_autotune(uw_mesh* m, uw_batch* b, const uw_physics* p, const char* 
   hipStream_t st = (hipStream_t)stream;
   const int nvar = nvar_of(p);
   char key[200];
-  std::snprintf(key, sizeof(key), "%lld %d %d %d %d %d %d", (long long)E.staged.N,
-                E.staged.n_inst, E.staged.n_tq, E.staged.n_tt, nvar, p->precision,
-                E.scheme.mode + 2 * E.scheme.vars);
+  // the workload's shape, independent of the tile size the tuning may change
+  std::snprintf(key, sizeof(key), "%lld %d %lld %lld %d %d %d", (long long)E.staged.N,
+                E.staged.n_inst, (long long)E.staged.rows_q, (long long)E.staged.rows_t, nvar,
+                p->precision, E.scheme.mode + 2 * E.scheme.vars);
   if (cache_path) {
     if (FILE* f = std::fopen(cache_path, "r")) {
       char line[320];
       bool found = false;
       int tile_found = uw::kTile;
       while (std::fgets(line, sizeof(line), f)) {
-        long long a;
-        int c1, c2, c3, c4, c5, c6, rq, rt, fl, tl;
-        if (std::sscanf(line, "%lld %d %d %d %d %d %d %d %d %d %d", &a, &c1, &c2, &c3, &c4, &c5,
-                        &c6, &rq, &rt, &fl, &tl) == 11) {
+        long long a, c2, c3;
+        int c1, c4, c5, c6, rq, rt, fl, tl;
+        if (std::sscanf(line, "%lld %d %lld %lld %d %d %d %d %d %d %d", &a, &c1, &c2, &c3, &c4,
+                        &c5, &c6, &rq, &rt, &fl, &tl) == 11) {
           char k2[200];
-          std::snprintf(k2, sizeof(k2), "%lld %d %d %d %d %d %d", a, c1, c2, c3, c4, c5, c6);
+          std::snprintf(k2, sizeof(k2), "%lld %d %lld %lld %d %d %d", a, c1, c2, c3, c4, c5, c6);
           if (std::strcmp(k2, key) == 0 && rq >= 0 && rt >= -1 && fl >= 0 &&
               uw::tile_size_ok(tl)) {
             E.sched = uw::Schedule{rq, rt, fl};
