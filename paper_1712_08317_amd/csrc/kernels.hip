@@ -54,13 +54,11 @@ struct Layout<3> {
 };
 
 // Reciprocal without the IEEE division sequence: v_rcp_f32 (1 ulp) in FP32;
-// in FP64 v_rcp_f64 refined by two Newton steps.
+// in FP64 v_rcp_f64 refined by one Newton step.
 __device__ inline float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp(double x) {
-  double r = __builtin_amdgcn_rcp(x);
-  r = fma(fma(-x, r, 1.0), r, r);
-  r = fma(fma(-x, r, 1.0), r, r);
-  return r;
+  const double r = __builtin_amdgcn_rcp(x);
+  return fma(fma(-x, r, 1.0), r, r);
 }
 
 // a / b and sqrt(x) in the flux: FP32 takes the hardware reciprocal and
