@@ -175,6 +175,28 @@ def cpu_baseline(seconds_hint=20.0):
                       f"(thread pools limited to 1; {busy:.2f} CPU-s per s measured)"}
 
 
+def copy_bandwidth():
+    """Achievable HBM rate on this device: a 1 GiB device-to-device copy
+    (bytes read plus bytes written over the time), median of five after a
+    warm-up copy, timed with events on torch's stream (the copy runs there)."""
+    import torch
+    a = torch.empty(1 << 27, dtype=torch.float64, device="cuda:0").fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    ms = []
+    for _ in range(5):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        b.copy_(a)
+        e1.record()
+        e1.synchronize()
+        ms.append(e0.elapsed_time(e1))
+    del a, b
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / (sorted(ms)[2] * 1e-3) / 1e9
+
+
 def host_cores():
     """CPUs this process may run on (its affinity mask), capped at the
     box's CPU share of one GPU (16)."""
@@ -465,6 +487,8 @@ def main():
         log(f"cpu baseline, {base['cores']} cores: {base['value']:.3g} cell-stage/s "
             f"({time.perf_counter() - t1:.1f} s)")
 
+    copy_gbs = copy_bandwidth()
+    log(f"device copy: {copy_gbs:.0f} GB/s")
     traffic = committed_traffic()
     out = {
         "metric": "cell-stage updates/s, FP32 vs FP64 at L1 err<=1e-5; % of HBM roofline",
@@ -503,7 +527,9 @@ def main():
                   "timing": f"value: graph replays of {chunk}-step calls; per-kernel times: a "
                             "second pass of as many steps launched one kernel at a time with HIP "
                             "events",
-                  "per_kernel_pass_ms_per_step": el_prof / args.steps * 1e3},
+                  "per_kernel_pass_ms_per_step": el_prof / args.steps * 1e3,
+                  "copy_GBs": copy_gbs,
+                  "frac_of_copy": sbytes / (el / args.steps / 3) / 1e9 / copy_gbs},
         "fp64_value": None if fp64 is None else fp64["value"],
         "fp64_ms_per_step": None if fp64 is None else fp64["ms_per_step"],
         "host_cores": host_cores(),
