@@ -61,6 +61,24 @@ __device__ inline double rcp(double x) {
   return fma(fma(-x, r, 1.0), r, r);
 }
 
+// Unnormalised weights of both signs of one candidate in FP64 (Sec. 3.4):
+// alpha+- = gamma+- / q+-^2, q = beta (1 + t + t^2) + eps with t = gamma
+// beta, written q = beta (t + t^2) + (beta + eps).  v_rcp_f64 occupies its
+// SIMD four times as long as an FMA and takes a Newton step, so both signs
+// share the reciprocal of the product q+^2 q-^2 (three more
+// multiplications; the product stays far inside the FP64 range).
+__device__ inline void alphas_fp64(double gp, double gm, double b, double bpe, double& ap,
+                                   double& am) {
+  double t = gp * b;
+  const double qp = fma(b, fma(t, t, t), bpe);
+  t = gm * b;
+  const double qm = fma(b, fma(t, t, t), bpe);
+  const double Qp = qp * qp, Qm = qm * qm;
+  const double r = rcp(Qp * Qm);
+  ap = gp * (Qm * r);
+  am = gm * (Qp * r);
+}
+
 // a / b and sqrt(x) in the flux: FP32 takes the hardware reciprocal and
 // square root (1 ulp; the correctly rounded sequences made the flux kernel 8%
 // slower once its face states came from LDS), FP64 the correctly rounded
@@ -310,17 +328,26 @@ __device__ inline void weno_cell(const TypeDev<T>& td, RowRef r, const WenoIn<T,
       for (int j = 0; j < M; ++j) {
         const T d = fma(ox, gx[j][v], oy * gy[j][v]);
         const T b = be[j][v];
-        // q = beta u + (beta + eps) with u = t + t^2, t = gamma beta
-        T t = gp[j] * b;
-        T q = fma(b, fma(t, t, t), bpe[j][v]);
-        T al = gp[j] * rcp(q * q);
-        Dp += al;
-        Np = fma(al, d, Np);
-        t = gm[j] * b;
-        q = fma(b, fma(t, t, t), bpe[j][v]);
-        al = gm[j] * rcp(q * q);
-        Dm += al;
-        Nm = fma(al, d, Nm);
+        if constexpr (sizeof(T) == 8) {
+          T ap, am;
+          alphas_fp64(gp[j], gm[j], b, bpe[j][v], ap, am);
+          Dp += ap;
+          Np = fma(ap, d, Np);
+          Dm += am;
+          Nm = fma(am, d, Nm);
+        } else {
+          // q = beta u + (beta + eps) with u = t + t^2, t = gamma beta
+          T t = gp[j] * b;
+          T q = fma(b, fma(t, t, t), bpe[j][v]);
+          T al = gp[j] * rcp(q * q);
+          Dp += al;
+          Np = fma(al, d, Np);
+          t = gm[j] * b;
+          q = fma(b, fma(t, t, t), bpe[j][v]);
+          al = gm[j] * rcp(q * q);
+          Dm += al;
+          Nm = fma(al, d, Nm);
+        }
       }
       R[v] = (T)w0[v] + (sp * (Np * rcp(Dp)) - sm * (Nm * rcp(Dm)));
     }
@@ -460,16 +487,25 @@ __device__ inline void weno_cell_char(const TypeDev<T>& td, RowRef r, const Weno
         for (int j = 0; j < M; ++j) {
           const T d = fma(ox[q], gx[j], oy[q] * gy[j]);
           const T b = be[j];
-          T t = gp[q][j] * b;
-          T qq = fma(b, fma(t, t, t), bpe[j]);
-          T al = gp[q][j] * rcp(qq * qq);
-          Dp += al;
-          Np = fma(al, d, Np);
-          t = gm[q][j] * b;
-          qq = fma(b, fma(t, t, t), bpe[j]);
-          al = gm[q][j] * rcp(qq * qq);
-          Dm += al;
-          Nm = fma(al, d, Nm);
+          if constexpr (sizeof(T) == 8) {
+            T ap, am;
+            alphas_fp64(gp[q][j], gm[q][j], b, bpe[j], ap, am);
+            Dp += ap;
+            Np = fma(ap, d, Np);
+            Dm += am;
+            Nm = fma(am, d, Nm);
+          } else {
+            T t = gp[q][j] * b;
+            T qq = fma(b, fma(t, t, t), bpe[j]);
+            T al = gp[q][j] * rcp(qq * qq);
+            Dp += al;
+            Np = fma(al, d, Np);
+            t = gm[q][j] * b;
+            qq = fma(b, fma(t, t, t), bpe[j]);
+            al = gm[q][j] * rcp(qq * qq);
+            Dm += al;
+            Nm = fma(al, d, Nm);
+          }
         }
         inc[q][c] = sp[q] * (Np * rcp(Dp)) - sm[q] * (Nm * rcp(Dm));
       }
