@@ -575,6 +575,19 @@ __device__ inline void linear_cell(const TypeDev<T>& td, RowRef r, const double*
 template <typename T, int NF, int KIND, int TILE>
 constexpr int kReconBlocksPerCu = (sizeof(T) == 4 && (NF == 3 || KIND != 1) ? 2 : 1) * 256 / TILE;
 
+// Face states in FS, face-major: the two Gauss-point states of face k of
+// cell i at fs_index(N, k, i), V values each (FS holds 4 N such pairs).
+// Consecutive cells' records of one face are adjacent, so that a wavefront
+// reading the neighbours across a tile edge (often consecutive cells of the
+// other tile, seen through the same face) shares cache lines.
+template <int V>
+__device__ inline int64_t fs_index(int64_t N, int k, int64_t i) {
+  return ((int64_t)k * N + i) * (2 * V);
+}
+// Copy unit of the records: 16 bytes, or 8 for the 8-byte FP32 scalar pair.
+template <typename T, int V>
+using FsUnit = typename std::conditional<(2 * V * sizeof(T) >= 16), int4, int2>::type;
+
 // One tile of cell type NF: stage its stencil values, reconstruct each
 // cell's Gauss-point states into LDS, write the tile's records out.
 template <typename T, int NF, int V, int KIND>
@@ -606,13 +619,18 @@ __device__ inline void recon_tile(const double* __restrict__ W, const MeshDev<T>
     }
   }
   __syncthreads();
-  // the tile's face states are contiguous in FS: copy them in 16-byte units
-  constexpr int U = REC / PER;            // 16-byte units per cell
-  const int n16 = tl.count * U;
-  int4* dst = reinterpret_cast<int4*>(FS + (int64_t)tl.first * REC);
-  for (int q = threadIdx.x; q < n16; q += blockDim.x) {
-    const int c = q / U, u = q - c * U;
-    dst[q] = *reinterpret_cast<const int4*>(fs_lds + c * STRIDE + u * PER);
+  // FS is face-major: face k of the tile's cells is one contiguous block,
+  // copied in units of 16 bytes (8 for FP32 scalar records)
+  using Unit = FsUnit<T, V>;
+  constexpr int PU = sizeof(Unit) / sizeof(T);   // values per unit
+  constexpr int FU = 2 * V / PU;                 // units per cell and face
+  const int n = tl.count * FU;
+  for (int k = 0; k < NF; ++k) {
+    Unit* dst = reinterpret_cast<Unit*>(FS + fs_index<V>(m.N, k, tl.first));
+    for (int q = threadIdx.x; q < n; q += blockDim.x) {
+      const int c = q / FU, u = q - c * FU;
+      dst[q] = *reinterpret_cast<const Unit*>(fs_lds + c * STRIDE + (2 * k * V + u * PU));
+    }
   }
   __syncthreads();   // the next tile overwrites both LDS regions
 }
@@ -786,20 +804,23 @@ __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
     const Tile tl = m.tiles[tile];
     const int nf = tile < m.n_tq ? 4 : 3;
     if (STAGE) {
-      // the units of each record that hold the 2 nf Gauss-point slots
-      const int U = (2 * nf * V + PER - 1) / PER;
-      const int n16 = tl.count * U;
-      const int4* src = reinterpret_cast<const int4*>(FS + (int64_t)tl.first * REC);
-      for (int q = threadIdx.x; q < n16; q += blockDim.x) {
-        const int c = q / U, u = q - c * U;
-        *reinterpret_cast<int4*>(rec + c * STRIDE + u * PER) = src[c * (REC / PER) + u];
+      // the tile's records, face by face, into one padded LDS row per cell
+      using Unit = FsUnit<T, V>;
+      constexpr int PU = sizeof(Unit) / sizeof(T);
+      constexpr int FU = 2 * V / PU;
+      const int n = tl.count * FU;
+      for (int k = 0; k < nf; ++k) {
+        const Unit* src = reinterpret_cast<const Unit*>(FS + fs_index<V>(N, k, tl.first));
+        for (int q = threadIdx.x; q < n; q += blockDim.x) {
+          const int c = q / FU, u = q - c * FU;
+          *reinterpret_cast<Unit*>(rec + c * STRIDE + (2 * k * V + u * PU)) = src[q];
+        }
       }
     }
     __syncthreads();
     double bound = INFINITY;
     if ((int)threadIdx.x < tl.count) {
       const int64_t i = tl.first + threadIdx.x;
-      const T* own = STAGE ? rec + threadIdx.x * STRIDE : FS + i * REC;
       double acc[V];
 #pragma unroll
       for (int v = 0; v < V; ++v) acc[v] = 0.0;
@@ -810,8 +831,9 @@ __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
         const T ny = m.fnrm[(k * 2 + 1) * N + i];
         const double coef = m.fcoef[k * N + i];
         T o0[V], o1[V], t0[V], t1[V];
-        load_state<T, V>(own + 2 * k * V, o0);
-        load_state<T, V>(own + (2 * k + 1) * V, o1);
+        const T* own = STAGE ? rec + threadIdx.x * STRIDE + 2 * k * V : FS + fs_index<V>(N, k, i);
+        load_state<T, V>(own, o0);
+        load_state<T, V>(own + V, o1);
         bool left = true;
         if (pk < 0) {
           // boundary face: the outside states (the stored normal is the cell's)
@@ -823,10 +845,11 @@ __global__ __launch_bounds__(TILE) void k_flux(MeshDev<T> m, PhysDev p,
           left = (pk & 1) != 0;
           // the neighbour's Gauss points run the other way along the face
           const int64_t lc = c - tl.first;
-          const T* nb =
-              STAGE && (uint64_t)lc < (uint64_t)tl.count ? rec + lc * STRIDE : FS + c * REC;
-          load_state<T, V>(nb + (2 * kp + 1) * V, t0);
-          load_state<T, V>(nb + 2 * kp * V, t1);
+          const T* nb = STAGE && (uint64_t)lc < (uint64_t)tl.count
+                            ? rec + lc * STRIDE + 2 * kp * V
+                            : FS + fs_index<V>(N, kp, c);
+          load_state<T, V>(nb + V, t0);
+          load_state<T, V>(nb, t1);
         }
         if constexpr (V == 4) {
           // an inadmissible reconstruction (the scheme is not positivity

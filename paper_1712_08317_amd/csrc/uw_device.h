@@ -114,7 +114,8 @@ struct Schedule {
 template <typename T>
 size_t recon_lds(int maxlen, int nvar, int tile);
 
-// Face states at the Gauss points: FS[(i*8 + g)*V + v].
+// Face states at the Gauss points, face-major: Gauss point q of face k of
+// cell i, variable v, at FS[((k*N + i)*2 + q)*V + v] (4 N V pairs).
 template <typename T>
 hipError_t launch_recon(const MeshDev<T>& m, const SchemeDev& s, const PhysDev& p,
                         const Schedule& sch, int nvar, const double* W, T* FS,
