@@ -399,9 +399,9 @@ def test_graph_cache_keeps_a_bounded_number_of_graphs():
 def test_one_reconstruction_launch_for_both_cell_types(prec, scheme, tile):
     """Schedule (q, -1, f): both cell types reconstructed by one launch (any
     number of persistent blocks, each taking quadrilateral and triangle
-    tiles) give the residual of the separate launches bit for bit; the FP32
-    linear scheme, whose two kernels differ in occupancy, keeps separate
-    launches."""
+    tiles) give the residual of the separate launches bit for bit, for the
+    Euler equations and scalar advection; the FP32 linear scheme, whose two
+    kernels differ in occupancy, keeps separate launches."""
     if tile == 512 and (prec != "fp32" or scheme != "weno"):
         pytest.skip("512-cell tiles: FP32 WENO on the conserved variables only")
     import paper_1712_08317_amd as uw
@@ -415,12 +415,15 @@ def test_one_reconstruction_launch_for_both_cell_types(prec, scheme, tile):
             assert M.tile_size(tile) == tile
         W = wl.seeded_state(mesh, 4, 23) if not (name == "sod" and scheme == "linear") \
             else wl.initial_state("c3", mesh)
-        M.schedule((0, 0, 0))
-        ref = gpu_residual(uw, M, W, "euler", prec)
-        for q in (0, 2, 256):
-            assert M.schedule((q, -1, 0)) == (q, -1, 0)
-            got = gpu_residual(uw, M, W, "euler", prec)
-            assert np.array_equal(got, ref), (name, q)
+        equations = ["euler"] + (["advection"] if scheme != "characteristic" else [])
+        for eq in equations:
+            Wq = W if eq == "euler" else W[:1].copy()
+            M.schedule((0, 0, 0))
+            ref = gpu_residual(uw, M, Wq, eq, prec)
+            for q in (0, 2, 256):
+                assert M.schedule((q, -1, 0)) == (q, -1, 0)
+                got = gpu_residual(uw, M, Wq, eq, prec)
+                assert np.array_equal(got, ref), (name, eq, q)
         with pytest.raises(uw.UwError) as e:
             M.schedule((0, -2, 0))
         assert e.value.status == uw.UW_EINVAL
