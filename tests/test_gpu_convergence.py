@@ -53,3 +53,39 @@ def test_density_wave_converges_at_third_order(kind, sizes):
     rel = float(np.abs(W32 - W).sum() / np.abs(W).sum())
     print(kind, "fp32 vs fp64 at t = 0.5, relative L1", rel, flush=True)
     assert rel <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_paper_accuracy_table_on_regular_quadrilaterals(prec):
+    """The paper's density-wave table for regular quadrilateral meshes
+    (Sec. 4.1, Table tab-accuracy1; stored in tests/golden): t = 2 with
+    dt = 0.3 h on n x n uniform squares of [0,2]^2, h = 1/8 to 1/64.  The
+    device's L1 (integral over the domain) and Linf density errors against
+    the exact cell averages are within 2.5% of the printed ones, in both
+    precisions."""
+    import os
+    import torch
+    import paper_1712_08317_amd as uw
+    gold = os.path.join(os.path.dirname(__file__), "golden", "paper_accuracy_regular_quads.txt")
+    for h, p_l1, p_linf in np.loadtxt(gold, comments="#"):
+        n = int(round(2.0 / h))
+        mesh = wl.grid_mesh(n, n, 2.0, 2.0, "quad", 0.0, 1, True, name=f"acc{n}")
+        M = uw.Mesh.from_workload(mesh, device=0)
+        M.precompute()
+        W0 = wl.cell_averages(mesh, wl.density_wave_euler(0.0), 4, q=4)
+        W = torch.from_numpy(M.to_internal(W0)).to("cuda:0")
+        t = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        steps = int(round(2.0 / (0.3 * h)))
+        ph = physics_for(uw, "euler", prec)
+        for _ in range(steps):
+            M.rk3_step(ph, W, t, dt_fixed=2.0 / steps, t_end=2.0)
+        M.check()
+        assert abs(t.item() - 2.0) < 1e-12
+        Wh = M.to_original(W.cpu().numpy())
+        ex = wl.cell_averages(mesh, wl.density_wave_euler(2.0), 4, q=4)[0]
+        area = wl.signed_areas(mesh.node_xy, mesh.cell_nodes)
+        e = np.abs(Wh[0] - ex)
+        l1, linf = float((area * e).sum()), float(e.max())
+        print(prec, f"h = 1/{n // 2}: L1 {l1:.4e} (paper {p_l1:.3e}), Linf {linf:.4e} "
+              f"(paper {p_linf:.3e})", flush=True)
+        assert abs(l1 / p_l1 - 1) < 0.025 and abs(linf / p_linf - 1) < 0.025
