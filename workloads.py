@@ -324,6 +324,25 @@ def wave_vortex_euler(strength: float = 5.0, centre=(1.0, 1.0), scale: float = 5
     return f
 
 
+def isentropic_vortex(t: float = 0.0, strength: float = 5.0, centre=(5.0, 5.0),
+                      period: float = 10.0, gamma=GAMMA):
+    """The paper's isentropic vortex (Sec. 4.1): mean flow (1, 1, 1, 1) plus
+    (du, dv) = s/(2 pi) e^{(1 - r^2)/2} (-yb, xb), dT = -(gamma - 1) s^2
+    / (8 gamma pi^2) e^{1 - r^2}, isentropic, advected by the mean flow to
+    time t on a periodic square of side ``period`` (nearest image)."""
+    def f(x, y):
+        xb = (x - centre[0] - t + period / 2) % period - period / 2
+        yb = (y - centre[1] - t + period / 2) % period - period / 2
+        r2 = xb * xb + yb * yb
+        du = strength / (2 * np.pi) * np.exp(0.5 * (1 - r2)) * (-yb)
+        dv = strength / (2 * np.pi) * np.exp(0.5 * (1 - r2)) * xb
+        dT = -(gamma - 1) * strength ** 2 / (8 * gamma * np.pi ** 2) * np.exp(1 - r2)
+        rho = (1 + dT) ** (1 / (gamma - 1))
+        p = (1 + dT) ** (gamma / (gamma - 1))
+        return primitive_to_conserved(rho, 1.0 + du, 1.0 + dv, p, gamma)
+    return f
+
+
 def rotated_sod(angle_deg: float = 30.0, gamma=GAMMA):
     """Sod states (1,0,0,1) | (0.125,0,0,0.1) across the line through
     (0.5,0.5) with unit normal (cos a, sin a); left where (x-0.5,y-0.5).n < 0."""
